@@ -1,0 +1,211 @@
+/*
+ * rqrcp.h -- C ABI of the MI355X (gfx950) randomized column-pivoted QR library.
+ *
+ * Method: Duersch & Gu, "Randomized Projection for Rank-Revealing Matrix
+ * Factorizations and Low-Rank Approximations" (arXiv:2008.04447).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major.  Element (i, j) of X with leading dimension ldx
+ *   is X[i + j * ldx].  Sizes and leading dimensions are int64_t.
+ * - Every matrix/vector pointer is a DEVICE pointer on the handle's device,
+ *   allocated and owned by the caller.  The library owns only its workspace,
+ *   which lives in the handle, grows on demand (hipMalloc) and is freed by
+ *   rq_destroy.
+ * - Calls are asynchronous on the handle's stream: they validate arguments on
+ *   the host, enqueue kernels and return.  Outputs are valid once the stream
+ *   has been synchronized (rq_sync_status does that and reports device-side
+ *   errors).  One handle must not be used from two host threads at once;
+ *   separate handles are independent.
+ * - Return value (rq_status): RQ_OK (0); a negative value -i when argument i
+ *   (1-based, counting the handle as argument 1) is invalid, checked before
+ *   anything is enqueued; or one of the positive RQ_E_* codes below.
+ * - Indices are 0-based.  jpvt[j] = c means column j of A P is column c of A.
+ * - Householder vectors follow the paper's reflector (Section 2): for a column
+ *   x, beta = -sign(x_0) ||x|| with sign(0) = +1, H = I - tau v v^T with
+ *   v_0 = 1 and tau = (beta - x_0) / beta; an all-zero column gives tau = 0.
+ * - Omega is the (b + p) x m Gaussian compression matrix of the sketch
+ *   B = Omega A (Section 3).  It is always passed explicitly; the library draws
+ *   no random numbers.
+ */
+#ifndef RQRCP_H
+#define RQRCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rq_status;
+
+enum {
+  RQ_OK = 0,
+  RQ_E_HIP = 1001,         /* a HIP runtime call failed                        */
+  RQ_E_NOMEM = 1002,       /* workspace allocation failed                      */
+  RQ_E_UNSUPPORTED = 1003, /* valid arguments outside this build's limits      */
+  RQ_E_DEVICE = 1004       /* reported by rq_sync_status: see device_error bits */
+};
+
+/* device_error bits reported by rq_sync_status */
+enum {
+  RQ_DEV_BARRIER_TIMEOUT = 1, /* a cross-workgroup wait exceeded its bound */
+  RQ_DEV_NONFINITE = 2,       /* NaN/Inf met in a norm or pivot decision   */
+  RQ_DEV_NO_PIVOT = 4         /* no admissible pivot column was found      */
+};
+
+/* Arithmetic of the bulk contractions.  The panel factorization, the norms
+ * and the sample QRCP are FP64 in both modes. */
+typedef enum {
+  RQ_FP64 = 0,        /* everything in FP64                                   */
+  RQ_MIXED_BF16 = 1   /* sketch and bulk inner products on BF16 MFMA, FP32
+                         accumulation; A given in FP32                        */
+} rq_prec;
+
+typedef struct rq_handle_s* rq_handle;
+
+/* Library limits of this build (checked by every entry point):
+ * 1 <= b <= 64, p >= 0, b + p <= 96, n <= 65536. */
+#define RQ_MAX_B 64
+#define RQ_MAX_ELL 96
+#define RQ_MAX_N 65536
+
+/* Create a handle on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The stream is borrowed:
+ * the caller keeps ownership and must keep it alive while the handle is used.
+ * Errors: -1 h == NULL, -2 bad device, RQ_E_HIP. */
+rq_status rq_create(rq_handle* h, int device, void* hip_stream);
+
+/* Release the handle and its workspace (waits for its stream first). */
+rq_status rq_destroy(rq_handle h);
+
+/* Re-point the handle at another stream of the same device. */
+rq_status rq_set_stream(rq_handle h, void* hip_stream);
+
+/* Wait for all work enqueued through `h`, then report and clear the device
+ * status word: *device_error receives an OR of RQ_DEV_* bits (0 = clean) and
+ * the call returns RQ_E_DEVICE when it is nonzero.  device_error may be NULL. */
+rq_status rq_sync_status(rq_handle h, int64_t* device_error);
+
+/* Last HIP error string seen by the handle (static storage, never NULL). */
+const char* rq_last_error(rq_handle h);
+
+/*
+ * rqrcp_factor -- RQRCP, Algorithm 4 (Section 3.4), with the sample update
+ * formula eq. (update1): B1 = S12 - S11 R11^{-1} R12, B2 = S22.
+ *
+ * Factors the first k columns of A P = Q R blockwise with blocks of b pivots
+ * chosen by a partial QRCP of the (b+p) x n_J sample, updating the sample
+ * instead of re-projecting.  k = min(m, n) is the full factorization.
+ *
+ *  m, n      rows and columns of A (m, n >= 0)
+ *  k         number of reflectors, 0 <= k <= min(m, n)
+ *  b, p      block size and oversampling; ell = b + p rows of Omega (ell <= m)
+ *  A, lda    in: A (m x n).  out: LAPACK geqp3 layout -- rows 0..k-1 hold R on
+ *            and above the diagonal, reflector tails below the diagonal of the
+ *            first k columns (unit diagonal implicit), and rows k..m-1 of
+ *            columns k..n-1 hold the transformed trailing matrix.  lda >= m.
+ *  Omega, ldo  in: ell x m compression matrix, ldo >= ell.  Not modified.
+ *  jpvt      out[n]: column permutation (0-based).
+ *  tau       out[k]: reflector coefficients.
+ *  T, ldt    out: b x k block-T (like dgeqrt): for the block starting at column
+ *            c0 with width bJ, T[0:bJ, c0:c0+bJ] is upper triangular with
+ *            H_c0 ... H_{c0+bJ-1} = I - Y_J T_J Y_J^T.  ldt >= b.  May be NULL.
+ * Argument numbers for errors: h=1 m=2 n=3 k=4 b=5 p=6 A=7 lda=8 Omega=9
+ * ldo=10 jpvt=11 tau=12 T=13 ldt=14.
+ */
+rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
+                       double* A, int64_t lda, const double* Omega, int64_t ldo,
+                       int64_t* jpvt, double* tau, double* T, int64_t ldt);
+
+/*
+ * qrcp_factor -- plain column-pivoted QR on the GPU, Algorithm 2 (QRCP with
+ * BLAS-3 reflection blocking, Section 2.1): every pivot is the column of
+ * largest trailing 2-norm of the full matrix, the column is brought up to date
+ * with the block's earlier reflectors, and the adjusted inner products
+ * w_j^T = tau_j (y_j^T A - (y_j^T Y) W^T) pass over the whole trailing matrix.
+ * Norms are downdated and recomputed when cancellation makes the downdate
+ * unreliable.  This is the baseline RQRCP is measured against.
+ *
+ * Same layout and meaning of A, jpvt, tau as rqrcp_factor; nb is the
+ * reflection block size (1 <= nb <= 64).
+ * Argument numbers: h=1 m=2 n=3 k=4 nb=5 A=6 lda=7 jpvt=8 tau=9.
+ */
+rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t nb,
+                      double* A, int64_t lda, int64_t* jpvt, double* tau);
+
+/*
+ * trqrcp_truncate -- truncated RQRCP without trailing update, Algorithm 5
+ * (Section 4.1).  A is never modified.  The selected columns are rebuilt from
+ * A - Y W^T just before their panel QR, the inner products use the
+ * block-reflector composition W2^T = T2^T (Y2^T A - (Y2^T Y1) W1^T), and the
+ * new rows of R are rebuilt from A - Y W^T before the sample update.
+ *
+ *  prec      RQ_FP64: A is double.  RQ_MIXED_BF16: A is float; the sketch and
+ *            Y2^T A run on BF16 MFMA (round-to-nearest-even inputs, FP32
+ *            accumulation), everything else in FP64.
+ *  m, n, k, b, p   as rqrcp_factor, k <= min(m, n); k < b is allowed (then the
+ *            single block uses bJ = k, Algorithm 3's single-sample case).
+ *  A, lda    in: A (m x n), double or float per prec.
+ *  Omega, ldo  in: ell x m, double.
+ *  jpvt      out[n]: first k entries are the selected columns.
+ *  Y, ldy    out: m x k double, reflectors with explicit unit diagonal and
+ *            zeros above it (ldy >= m).
+ *  T, ldt    out: k x k double upper triangular, Q = I - Y T Y^T (ldt >= k).
+ *  R, ldr    out: k x n double, columns in pivoted order: A P ~ Q[:, :k] R
+ *            (ldr >= k).
+ * Argument numbers: h=1 prec=2 m=3 n=4 k=5 b=6 p=7 A=8 lda=9 Omega=10 ldo=11
+ * jpvt=12 Y=13 ldy=14 T=15 ldt=16 R=17 ldr=18.
+ */
+rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
+                          int64_t b, int64_t p, const void* A, int64_t lda,
+                          const double* Omega, int64_t ldo, int64_t* jpvt,
+                          double* Y, int64_t ldy, double* T, int64_t ldt,
+                          double* R, int64_t ldr);
+
+/*
+ * tuxv_svd -- TUXV approximation of the truncated SVD, Algorithm 6 with
+ * j_max = 1 (Section 4.2): TRQRCP, Z0 = R P^T, LQ of Z0 (QR of Z0^T) giving
+ * V (n x k), Z1 = A V, QR of Z1 giving U (m x k) and X (k x k upper), so that
+ * A ~ U X V^T (eq. TUXV).  The paper's unused tau argument is dropped.
+ *
+ *  prec, m, n, k, b, p, A, lda, Omega, ldo   as trqrcp_truncate.
+ *  U, ldu    out: m x k double with orthonormal columns (ldu >= m).
+ *  X, ldx    out: k x k double upper triangular (ldx >= k).
+ *  V, ldv    out: n x k double with orthonormal columns (ldv >= n).
+ *  jpvt      out[n]: TRQRCP's column permutation.
+ * Argument numbers: h=1 prec=2 m=3 n=4 k=5 b=6 p=7 A=8 lda=9 Omega=10 ldo=11
+ * U=12 ldu=13 X=14 ldx=15 V=16 ldv=17 jpvt=18.
+ */
+rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
+                   int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
+                   double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
+                   int64_t* jpvt);
+
+/*
+ * rq_sketch -- the sketch B = Omega A alone (the first step of Algorithms 3-5).
+ *  prec      RQ_FP64 (A double) or RQ_MIXED_BF16 (A float, BF16 MFMA).
+ *  ell, m, n sizes: Omega is ell x m, A is m x n, B is ell x n (double).
+ * Argument numbers: h=1 prec=2 ell=3 m=4 n=5 Omega=6 ldo=7 A=8 lda=9 B=10 ldb=11.
+ */
+rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n,
+                    const double* Omega, int64_t ldo, const void* A, int64_t lda,
+                    double* B, int64_t ldb);
+
+/*
+ * rq_sample_qrcp -- QRCP(B, b) of Algorithm 4 on its own: `steps` pivots of
+ * the ell x n sample B chosen by largest trailing 2-norm (ties: lowest current
+ * position), with every column transformed.  On exit B holds
+ * [[S11, S12], [0, S22]] in pivoted column order (zeros below the diagonal of
+ * the first `steps` columns), and perm[j] (j < n) is the input position of
+ * the column now at position j.
+ * Argument numbers: h=1 ell=2 n=3 steps=4 B=5 ldb=6 perm=7.
+ */
+rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, double* B,
+                         int64_t ldb, int64_t* perm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RQRCP_H */

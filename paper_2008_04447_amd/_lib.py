@@ -1,0 +1,66 @@
+"""ctypes view of ``librqrcp.so`` (the C ABI in include/rqrcp.h).
+
+Argument marshalling only: every step of the factorizations runs in the HIP
+library.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librqrcp.so")
+
+c_i64 = ctypes.c_int64
+c_p = ctypes.c_void_p
+
+# (name, restype, argtypes) for every exported entry point of include/rqrcp.h
+SIGNATURES = {
+    "rq_create": (ctypes.c_int32, [ctypes.POINTER(c_p), ctypes.c_int, c_p]),
+    "rq_destroy": (ctypes.c_int32, [c_p]),
+    "rq_set_stream": (ctypes.c_int32, [c_p, c_p]),
+    "rq_sync_status": (ctypes.c_int32, [c_p, ctypes.POINTER(c_i64)]),
+    "rq_last_error": (ctypes.c_char_p, [c_p]),
+    "rqrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
+                                      c_i64, c_p, c_p, c_p, c_i64]),
+    "qrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p, c_p]),
+    "trqrcp_truncate": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_i64, c_i64,
+                                         c_p, c_i64, c_p, c_i64, c_p, c_p, c_i64, c_p, c_i64,
+                                         c_p, c_i64]),
+    "tuxv_svd": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_i64, c_i64, c_p,
+                                  c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p]),
+    "rq_sketch": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
+                                   c_i64, c_p, c_i64]),
+    "rq_sample_qrcp": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_p, c_i64, c_p]),
+}
+
+RQ_OK = 0
+RQ_E_HIP = 1001
+RQ_E_NOMEM = 1002
+RQ_E_UNSUPPORTED = 1003
+RQ_E_DEVICE = 1004
+RQ_FP64 = 0
+RQ_MIXED_BF16 = 1
+
+_lib = None
+
+
+def load():
+    """Load librqrcp.so and declare every signature; raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class RQError(RuntimeError):
+    def __init__(self, fn, code, detail=""):
+        self.code = code
+        super().__init__(f"{fn} returned {code}{(': ' + detail) if detail else ''}")

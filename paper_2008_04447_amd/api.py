@@ -1,0 +1,189 @@
+"""Thin Python binding of the C ABI (argument marshalling only).
+
+Matrices are torch tensors on a HIP device in column-major layout: a (m, n)
+tensor with strides (1, ld).  ``colmajor`` / ``empty_colmajor`` produce them.
+PyTorch supplies device memory and the stream; every computation runs in
+librqrcp.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import RQ_FP64, RQ_MIXED_BF16, RQError
+
+_DT = {torch.float64: RQ_FP64, torch.float32: RQ_MIXED_BF16}
+
+
+def empty_colmajor(m, n, dtype=torch.float64, device="cuda"):
+    return torch.empty((max(n, 1), max(m, 1)), dtype=dtype, device=device).t()[:m, :n]
+
+
+def colmajor(a, dtype=torch.float64, device="cuda"):
+    """Column-major device copy of a 2-D array (numpy or torch)."""
+    src = torch.as_tensor(a, dtype=dtype)
+    m, n = src.shape
+    out = empty_colmajor(m, n, dtype, device)
+    out.copy_(src)
+    return out
+
+
+def ld(t):
+    """Leading dimension of a column-major 2-D tensor (checks the layout)."""
+    m, n = t.shape
+    if n > 1 and m > 1 and t.stride(0) != 1:
+        raise ValueError("tensor is not column-major (stride(0) must be 1)")
+    return max(1, t.stride(1) if n > 1 else m)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(fn, rc, h=None):
+    if rc != 0:
+        detail = ""
+        if h is not None and h.ptr:
+            detail = (_lib.load().rq_last_error(h.ptr) or b"").decode(errors="replace")
+        raise RQError(fn, rc, detail)
+
+
+class Handle:
+    """Library handle bound to a device and a stream (default: current stream)."""
+
+    def __init__(self, device=0, stream=None):
+        lib = _lib.load()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self.device.index or 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ptr = ctypes.c_void_p()
+        _check("rq_create", lib.rq_create(ctypes.byref(self.ptr), idx,
+                                          ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check("rq_set_stream", _lib.load().rq_set_stream(self.ptr, ctypes.c_void_p(stream.cuda_stream)))
+
+    def sync(self):
+        """Wait for the stream; raise RQError(RQ_E_DEVICE) on a device-side error."""
+        err = ctypes.c_int64(0)
+        rc = _lib.load().rq_sync_status(self.ptr, ctypes.byref(err))
+        if rc != 0:
+            raise RQError("rq_sync_status", rc, f"device_error bits = {err.value}")
+        return 0
+
+    def close(self):
+        if self.ptr:
+            _lib.load().rq_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def default_handle(device=None):
+    dev = torch.cuda.current_device() if device is None else device
+    stream = torch.cuda.current_stream(dev)
+    h = _default.get(dev)
+    if h is None:
+        h = Handle(dev, stream)
+        _default[dev] = h
+    elif h.stream.cuda_stream != stream.cuda_stream:
+        h.set_stream(stream)
+    return h
+
+
+def rqrcp_factor(A, Omega, b, p, k=None, handle=None):
+    """RQRCP (Algorithm 4) in place on the column-major float64 tensor A.
+
+    Returns (jpvt, tau, T) as device tensors; A holds R and the reflectors.
+    """
+    h = handle or default_handle(A.device.index)
+    m, n = A.shape
+    k = min(m, n) if k is None else int(k)
+    dev = A.device
+    jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
+    tau = torch.empty(max(k, 1), dtype=torch.float64, device=dev)[:k]
+    T = empty_colmajor(b, max(k, 1), torch.float64, dev)
+    rc = _lib.load().rqrcp_factor(h.ptr, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
+                                  ld(Omega), _ptr(jpvt), _ptr(tau), _ptr(T), ld(T))
+    _check("rqrcp_factor", rc, h)
+    return jpvt, tau, T
+
+
+def qrcp_factor(A, k=None, nb=32, handle=None):
+    """Plain QRCP (Algorithm 2) in place on A; returns (jpvt, tau)."""
+    h = handle or default_handle(A.device.index)
+    m, n = A.shape
+    k = min(m, n) if k is None else int(k)
+    dev = A.device
+    jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
+    tau = torch.empty(max(k, 1), dtype=torch.float64, device=dev)[:k]
+    rc = _lib.load().qrcp_factor(h.ptr, m, n, k, nb, _ptr(A), ld(A), _ptr(jpvt), _ptr(tau))
+    _check("qrcp_factor", rc, h)
+    return jpvt, tau
+
+
+def trqrcp_truncate(A, Omega, b, p, k, handle=None):
+    """TRQRCP (Algorithm 5).  A float64 (FP64 path) or float32 (mixed BF16 path).
+
+    Returns (jpvt, Y, T, R)."""
+    h = handle or default_handle(A.device.index)
+    m, n = A.shape
+    dev = A.device
+    prec = _DT[A.dtype]
+    jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
+    Y = empty_colmajor(m, k, torch.float64, dev)
+    T = empty_colmajor(k, k, torch.float64, dev)
+    R = empty_colmajor(k, n, torch.float64, dev)
+    rc = _lib.load().trqrcp_truncate(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
+                                     ld(Omega), _ptr(jpvt), _ptr(Y), ld(Y), _ptr(T), ld(T),
+                                     _ptr(R), ld(R))
+    _check("trqrcp_truncate", rc, h)
+    return jpvt, Y, T, R
+
+
+def tuxv_svd(A, Omega, b, p, k, handle=None):
+    """TUXV (Algorithm 6, j_max = 1).  Returns (U, X, V, jpvt) with A ~ U X V^T."""
+    h = handle or default_handle(A.device.index)
+    m, n = A.shape
+    dev = A.device
+    prec = _DT[A.dtype]
+    U = empty_colmajor(m, k, torch.float64, dev)
+    X = empty_colmajor(k, k, torch.float64, dev)
+    V = empty_colmajor(n, k, torch.float64, dev)
+    jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
+    rc = _lib.load().tuxv_svd(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega), ld(Omega),
+                              _ptr(U), ld(U), _ptr(X), ld(X), _ptr(V), ld(V), _ptr(jpvt))
+    _check("tuxv_svd", rc, h)
+    return U, X, V, jpvt
+
+
+def sketch(Omega, A, handle=None):
+    """B = Omega A (ell x n, float64) on the device."""
+    h = handle or default_handle(A.device.index)
+    ell, m = Omega.shape
+    n = A.shape[1]
+    B = empty_colmajor(ell, n, torch.float64, A.device)
+    rc = _lib.load().rq_sketch(h.ptr, _DT[A.dtype], ell, m, n, _ptr(Omega), ld(Omega), _ptr(A),
+                               ld(A), _ptr(B), ld(B))
+    _check("rq_sketch", rc, h)
+    return B
+
+
+def sample_qrcp(B, steps, handle=None):
+    """QRCP(B, steps) in place on the sample B; returns perm (final <- input position)."""
+    h = handle or default_handle(B.device.index)
+    ell, n = B.shape
+    perm = torch.empty(max(n, 1), dtype=torch.int64, device=B.device)[:n]
+    rc = _lib.load().rq_sample_qrcp(h.ptr, ell, n, steps, _ptr(B), ld(B), _ptr(perm))
+    _check("rq_sample_qrcp", rc, h)
+    return perm

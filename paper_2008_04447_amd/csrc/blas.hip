@@ -1,0 +1,363 @@
+// FP64 MFMA contractions and the small kernels of the block loop:
+//   * gemm_lx  : D(P x N) = L(P x K) X(K x N) with short P (the sketch Omega A,
+//                the inner products Y^T A, and the sample update S12 - M R12);
+//   * reduce   : fixed-order sum of split-K partials, optionally Z = T^T W;
+//   * update   : trailing update C -= Y Z (the block reflection of Algorithm 4);
+//   * omega11  : Omega_hat_11 = S11 R11^{-1} (eq. update1);
+//   * permute  : column permutation of a block of pivots.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace rq {
+
+// ---------------------------------------------------------------------------
+// gemm_lx: each workgroup owns 64 output columns (16 per wave) and all P rows
+// (PB blocks of 16), over one K chunk.  The K index of MFMA step s in lane l is
+// k0 + 4 * (l / 16) + s, so each lane reads 4 consecutive rows of X per group of
+// 16 k values (both operands use the same ordering of k).
+template <int PB>
+__global__ __launch_bounds__(256) void gemm_lx_kernel(GemmArgs g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + wave * 16 + (lane & 15);
+  const int kq = lane >> 4;
+  const int kb = blockIdx.y * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  const bool nok = n < g.N;
+  dx4 acc[PB];
+#pragma unroll
+  for (int i = 0; i < PB; ++i) acc[i] = dx4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    double xb[4];
+    double la[PB][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * kq + s;
+      xb[s] = (nok && k < ke) ? g.X[k + (int64_t)n * g.ldx] : 0.0;
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int p = 16 * i + (lane & 15);
+        la[i][s] = (p < g.P && k < ke) ? g.L[(int64_t)p * g.sLp + (int64_t)k * g.sLk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < PB; ++i) acc[i] = mfma_f64(la[i][s], xb[s], acc[i]);
+  }
+  if (!nok) return;
+  if (g.ksplit > 1) {
+    double* o = g.out + (int64_t)blockIdx.y * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * i + kq + 4 * v;
+        if (p < g.P) o[p + (int64_t)n * g.ldout] = acc[i][v];
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * i + kq + 4 * v;
+        if (p < g.P) {
+          double r = g.alpha * acc[i][v];
+          if (g.beta != 0.0) r += g.beta * g.C[p + (int64_t)n * g.ldc];
+          g.out[p + (int64_t)n * g.ldout] = r;
+        }
+      }
+  }
+}
+
+void plan_split(int K, int N, int* ksplit, int* kchunk) {
+  const int tiles = (N + 63) / 64;
+  int ks = (1024 + tiles - 1) / tiles;             // aim for ~4 workgroups per CU
+  const int kmax = (K + 255) / 256;                // at least 256 rows per chunk
+  if (ks > kmax) ks = kmax;
+  if (ks > 32) ks = 32;
+  if (ks < 1) ks = 1;
+  int kc = (K + ks - 1) / ks;
+  kc = ((kc + 15) / 16) * 16;
+  if (kc < 16) kc = 16;
+  ks = (K + kc - 1) / kc;
+  if (ks < 1) ks = 1;
+  *ksplit = ks;
+  *kchunk = kc;
+}
+
+hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
+  if (g.N <= 0 || g.P <= 0) return hipSuccess;
+  const int pb = (g.P + 15) / 16;
+  dim3 grid((g.N + 63) / 64, g.ksplit);
+  switch (pb) {
+    case 1: hipLaunchKernelGGL(gemm_lx_kernel<1>, grid, dim3(256), 0, s, g); break;
+    case 2: hipLaunchKernelGGL(gemm_lx_kernel<2>, grid, dim3(256), 0, s, g); break;
+    case 3: hipLaunchKernelGGL(gemm_lx_kernel<3>, grid, dim3(256), 0, s, g); break;
+    case 4: hipLaunchKernelGGL(gemm_lx_kernel<4>, grid, dim3(256), 0, s, g); break;
+    case 5: hipLaunchKernelGGL(gemm_lx_kernel<5>, grid, dim3(256), 0, s, g); break;
+    case 6: hipLaunchKernelGGL(gemm_lx_kernel<6>, grid, dim3(256), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reduce: out(p, n) = sum_s part_s(p, n) in order s = 0, 1, ...; with T the
+// column is then multiplied by T^T (T upper triangular bj x bj):
+// Z(i, n) = sum_{q <= i} T(q, i) W(q, n), rows bj..63 of Z set to zero.
+__global__ __launch_bounds__(256) void reduce_plain_kernel(const double* part, int64_t ldp,
+                                                           int64_t sstride, int ks, int P, int N,
+                                                           double* out, int64_t ldout) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)P * N) return;
+  const int p = (int)(e % P);
+  const int64_t n = e / P;
+  double s = 0.0;
+  for (int q = 0; q < ks; ++q) s += part[q * sstride + p + n * ldp];
+  out[p + n * ldout] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64_t ldp,
+                                                       int64_t sstride, int ks, int N,
+                                                       double* Z, const double* T, int64_t ldt,
+                                                       int bj) {
+  __shared__ double s_T[64][65];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = e % 64, q = e / 64;
+    s_T[i][q] = (i < bj && q < bj && i <= q) ? T[i + (int64_t)q * ldt] : 0.0;
+  }
+  __syncthreads();
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  double w[64];
+#pragma unroll
+  for (int q = 0; q < 64; ++q) {
+    double s = 0.0;
+    if (q < bj)
+      for (int r = 0; r < ks; ++r) s += part[r * sstride + q + n * ldp];
+    w[q] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q <= i; ++q) z += s_T[q][i] * w[q];
+    Z[i + n * 64] = (i < bj) ? z : 0.0;
+  }
+}
+
+hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P, int N,
+                         double* out, int64_t ldout, const double* T, int64_t ldt, int bj,
+                         hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  if (T) {
+    hipLaunchKernelGGL(reduce_t_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, ldp,
+                       sstride, ks, N, out, T, ldt, bj);
+  } else {
+    const int64_t total = (int64_t)P * N;
+    hipLaunchKernelGGL(reduce_plain_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       s, part, ldp, sstride, ks, P, N, out, ldout);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// update: C(M x N) -= Y(M x K) Z(K x N).  Each workgroup owns a 64 x 64 tile of
+// C; wave (wr, wc) owns 32 x 32 as 2 x 2 MFMA blocks computed as blocks of
+// C^T, so that for a fixed accumulator element the 16 lanes of a row touch 16
+// consecutive rows of one column of C (coalesced loads and stores).
+__global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int M, int N,
+                                                     const double* Y, int64_t ldy,
+                                                     const double* Z, int64_t ldz, int kpad) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rb = blockIdx.x * 64 + (wave & 1) * 32;
+  const int cb = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int l16 = lane & 15;
+  const int kq = lane >> 4;
+  dx4 acc[2][2];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int r = rb + 16 * ib + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cc = cb + 16 * jb + kq + 4 * v;
+        acc[ib][jb][v] = (r < M && cc < N) ? C[r + (int64_t)cc * ldc] : 0.0;
+      }
+    }
+  for (int k0 = 0; k0 < kpad; k0 += 16) {
+    double za[2][4], yb[2][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * kq + s;
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const int cc = cb + 16 * jb + l16;
+        za[jb][s] = (cc < N) ? -Z[k + (int64_t)cc * ldz] : 0.0;
+      }
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) {
+        const int r = rb + 16 * ib + l16;
+        yb[ib][s] = (r < M) ? Y[r + (int64_t)k * ldy] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = mfma_f64(za[jb][s], yb[ib][s], acc[ib][jb]);
+  }
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int r = rb + 16 * ib + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cc = cb + 16 * jb + kq + 4 * v;
+        if (r < M && cc < N) C[r + (int64_t)cc * ldc] = acc[ib][jb][v];
+      }
+    }
+}
+
+hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
+                         const double* Z, int64_t ldz, int bj, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int kpad = ((bj + 15) / 16) * 16;
+  dim3 grid((M + 63) / 64, (N + 63) / 64);
+  hipLaunchKernelGGL(update_kernel, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, Z, ldz, kpad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// omega11: one wave per row i of M = S11 R11^{-1}; lane c holds row i's
+// right-hand side entry c and column c of R11.  Column-oriented substitution:
+// m_c = s_c / R_cc, then s_c' -= m_c R_cc' for c' > c.
+__global__ __launch_bounds__(256) void omega11_kernel(const double* S11, int64_t lds,
+                                                      const double* R11, int64_t ldr, int bj,
+                                                      double* M, int64_t ldm) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= bj) return;
+  double rc[64];
+#pragma unroll
+  for (int q = 0; q < 64; ++q) rc[q] = (lane < bj && q <= lane) ? R11[q + (int64_t)lane * ldr] : 0.0;
+  double sv = (lane < bj && lane >= i) ? S11[i + (int64_t)lane * lds] : 0.0;
+  double mine = 0.0;
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    if (c < bj) {
+      const double d = __shfl(rc[c], c, 64);      // R11(c, c)
+      const double mc = __shfl(sv, c, 64) / d;
+      if (lane == c) mine = mc;
+      if (lane > c) sv -= mc * rc[c];             // rc[c] = R11(c, lane)
+    }
+  }
+  if (lane < bj) M[i + (int64_t)lane * ldm] = mine;
+}
+
+hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr, int bj,
+                          double* M, int64_t ldm, hipStream_t s) {
+  hipLaunchKernelGGL(omega11_kernel, dim3((bj + 3) / 4), dim3(256), 0, s, S11, lds, R11, ldr,
+                     bj, M, ldm);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// permute: new X(:, q) = X(:, src_top[q]) for q < bj and
+// new X(:, dst_low[o]) = X(:, o) for o < bj with dst_low[o] >= 0 (positions
+// relative to the block start).  Each workgroup stages 64 rows of all moved
+// columns in LDS before writing, and workgroups own disjoint rows.
+__global__ __launch_bounds__(256) void permute_kernel(double* X, int64_t ldx, int rows, int bj,
+                                                      const int* src_top, const int* dst_low,
+                                                      int64_t* jpvt) {
+  __shared__ double s_top[64][65];
+  __shared__ double s_low[64][65];
+  __shared__ int s_src[64], s_dst[64];
+  const int t = threadIdx.x;
+  if (t < 64) {
+    s_src[t] = (t < bj) ? src_top[t] : -1;
+    s_dst[t] = (t < bj) ? dst_low[t] : -1;
+  }
+  __syncthreads();
+  const int r0 = blockIdx.x * 64;
+  const int rr = t & 63;
+  const int r = r0 + rr;
+  for (int q = t >> 6; q < bj; q += 4) {
+    if (r < rows) {
+      s_top[q][rr] = X[r + (int64_t)s_src[q] * ldx];
+      s_low[q][rr] = (s_dst[q] >= 0) ? X[r + (int64_t)q * ldx] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int q = t >> 6; q < bj; q += 4) {
+    if (r < rows) {
+      X[r + (int64_t)q * ldx] = s_top[q][rr];
+      if (s_dst[q] >= 0) X[r + (int64_t)s_dst[q] * ldx] = s_low[q][rr];
+    }
+  }
+  if (jpvt && blockIdx.x == 0) {
+    __shared__ int64_t s_jt[64], s_jl[64];
+    if (t < bj) {
+      s_jt[t] = jpvt[s_src[t]];
+      s_jl[t] = jpvt[t];
+    }
+    __syncthreads();
+    if (t < bj) {
+      jpvt[t] = s_jt[t];
+      if (s_dst[t] >= 0) jpvt[s_dst[t]] = s_jl[t];
+    }
+  }
+}
+
+hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, const int* src_top,
+                          const int* dst_low, int64_t* jpvt, hipStream_t s) {
+  const int blocks = rows > 0 ? (rows + 63) / 64 : 1;
+  hipLaunchKernelGGL(permute_kernel, dim3(blocks), dim3(256), 0, s, X, ldx, rows, bj, src_top,
+                     dst_low, jpvt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void iota_kernel(int64_t* v, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+hipError_t launch_iota(int64_t* v, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+
+__global__ void zero_u32_kernel(uint32_t* v, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = 0u;
+}
+hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+
+__global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,
+                              int cols) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int r = (int)(e % rows);
+  const int64_t c = e / rows;
+  dst[r + c * ldd] = src[r + c * lds];
+}
+hipError_t launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,
+                         int cols, hipStream_t s) {
+  const int64_t total = (int64_t)rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src,
+                     lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+}  // namespace rq

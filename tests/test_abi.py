@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/rqrcp.h declares, and rejects invalid arguments on the host before any
+device work (LAPACK-style negative argument index)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rqrcp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:rq_status|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2008_04447_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("librqrcp.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ["rq_create", "rq_destroy", "rq_sync_status", "rqrcp_factor", "qrcp_factor",
+                 "trqrcp_truncate", "tuxv_svd", "rq_sketch", "rq_sample_qrcp"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2008_04447_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in declared_functions():
+        assert name in exported, name
+        assert name in _lib.SIGNATURES, name
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def test_null_handle_is_argument_one(lib):
+    assert lib.rq_destroy(None) == -1
+    assert lib.rqrcp_factor(None, 4, 4, 4, 2, 2, None, 4, None, 4, None, None, None, 2) == -1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, 2, 2), -2),          # m < 0
+    ((4, -1, 0, 2, 2), -3),          # n < 0
+    ((4, 4, 5, 2, 2), -4),           # k > min(m, n)
+    ((4, 4, 4, 0, 2), -5),           # b < 1
+    ((4, 4, 4, 65, 0), -5),          # b > 64
+    ((8, 4, 4, 2, -1), -6),          # p < 0
+    ((100, 4, 4, 64, 40), -6),       # ell > 96
+    ((4, 4, 4, 2, 4), -6),           # ell > m
+])
+def test_rqrcp_argument_validation(lib, args, code):
+    m, n, k, b, p = args
+    buf = ctypes.c_void_p(0x2000)
+    rc = lib.rqrcp_factor(FAKE, m, n, k, b, p, buf, max(1, m), buf, max(1, b + p), buf, buf,
+                          None, 0)
+    assert rc == code
+
+
+def test_rqrcp_leading_dimension_and_pointer_checks(lib):
+    buf = ctypes.c_void_p(0x2000)
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, None, 10, buf, 4, buf, buf, None, 0) == -7
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 9, buf, 4, buf, buf, None, 0) == -8
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, None, 4, buf, buf, None, 0) == -9
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 3, buf, buf, None, 0) == -10
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, None, buf, None, 0) == -11
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, buf, None, None, 0) == -12
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, buf, buf, buf, 1) == -14
+
+
+def test_sketch_and_sample_qrcp_validation(lib):
+    buf = ctypes.c_void_p(0x2000)
+    assert lib.rq_sketch(FAKE, 7, 4, 10, 5, buf, 4, buf, 10, buf, 4) == -2
+    assert lib.rq_sketch(FAKE, 0, 0, 10, 5, buf, 4, buf, 10, buf, 4) == -3
+    assert lib.rq_sketch(FAKE, 0, 4, 10, 5, buf, 3, buf, 10, buf, 4) == -7
+    assert lib.rq_sketch(FAKE, 0, 4, 10, 5, buf, 4, buf, 9, buf, 4) == -9
+    assert lib.rq_sample_qrcp(FAKE, 8, 10, 9, buf, 8, buf) == -4
+    assert lib.rq_sample_qrcp(FAKE, 8, 10, 4, buf, 7, buf) == -6

@@ -1,0 +1,183 @@
+"""GPU parity of the sketch, the sample QRCP and RQRCP against the FP64 oracle.
+
+Inputs are seeded synthetic matrices shaped like the paper's workloads.  Pivots
+must equal the oracle's exactly on the certified prefix (steps whose best and
+runner-up sample norms are separated beyond rounding); R rows must agree to
+1e-10 relative on that prefix; the GPU factorization must satisfy
+||AP - QR||_F / ||A||_F <= 1e-13 and ||Q^T Q - I|| <= 1e-13 on its own.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import q_from_inplace
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# Certificate thresholds: sample norms are recomputed exactly on both sides.
+REL, ABS = 1e-10, 1e-13
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2008_04447_amd import api as _api
+    return _api
+
+
+def _dev(api, x):
+    return api.colmajor(x, device=torch.device("cuda", 0))
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+# ----------------------------------------------------------------------------- sketch
+@pytest.mark.parametrize("ell,m,n", [(40, 1000, 1000), (72, 777, 300), (9, 50, 3000), (96, 4000, 70)])
+def test_sketch_matches_product(api, ell, m, n):
+    a = synth.gaussian((m, n), 1000 + m)
+    om = synth.omega(ell, m, 2000 + n)
+    B = api.sketch(_dev(api, om), _dev(api, a))
+    api.default_handle(0).sync()
+    ref = om @ a
+    bound = np.abs(om) @ np.abs(a)
+    err = np.abs(_host(B) - ref)
+    assert np.all(err <= 4 * m * 1.2e-16 * bound + 1e-300)
+
+
+# ----------------------------------------------------------------------------- sample QRCP
+@pytest.mark.parametrize("ell,n,steps", [(40, 1000, 32), (72, 8000, 64), (24, 257, 16), (8, 5, 5)])
+def test_sample_qrcp_matches_oracle(api, ell, n, steps):
+    b = synth.gaussian((ell, n), 3000 + n) * (1.0 + np.arange(n) % 7)[None, :]
+    B = _dev(api, b)
+    perm = api.sample_qrcp(B, steps)
+    api.default_handle(0).sync()
+    ref = oracle.partial_qrcp(b, steps)
+    scale = np.linalg.norm(b, axis=0).max()
+    pre = ref.trace.prefix(scale, REL, ABS)
+    assert pre >= min(steps, 8)
+    rperm = np.arange(n)
+    oracle.apply_transpositions(rperm, ref.pivots, axis=0)
+    gperm = _host(perm)
+    assert sorted(gperm) == list(range(n))
+    np.testing.assert_array_equal(gperm[:pre], rperm[:pre])
+    if pre == steps:
+        np.testing.assert_array_equal(gperm, rperm)
+        s = _host(B)
+        np.testing.assert_allclose(s, ref.s, atol=1e-12 * scale)
+
+
+# ----------------------------------------------------------------------------- RQRCP
+def _rqrcp_case(api, m, n, b, p, k, a, om):
+    A = _dev(api, a)
+    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, om), b, p, k)
+    api.default_handle(0).sync()
+    return _host(A), _host(jpvt), _host(tau), _host(T)
+
+
+def _check_against_oracle(a, om, b, p, k, qr, jpvt, tau, T, min_prefix):
+    m, n = a.shape
+    ref = oracle.rqrcp(a, om, b, p, k=k)
+    pre = ref.trace.prefix(ref.sample_scale, REL, ABS)
+    assert pre >= min_prefix, f"certified prefix only {pre}"
+    assert sorted(jpvt) == list(range(n))
+    np.testing.assert_array_equal(jpvt[:pre], ref.jpvt[:pre])
+    r_g = np.triu(qr[:k])
+    r_o = np.triu(ref.qr[:k])
+    rows = min(pre, k)
+    # Householder rounding errors are absolute (~ eps ||A||), so deep rows of a
+    # graded R get the floor 1e-12 ||A||_F on top of the relative 1e-10.
+    floor = 1e-12 * np.linalg.norm(a)
+    d = np.linalg.norm(r_g[:rows] - r_o[:rows], axis=1)
+    nrm = np.linalg.norm(r_o[:rows], axis=1)
+    bad = np.flatnonzero(d > 1e-10 * nrm + floor)
+    assert bad.size == 0, (f"R rows {bad[:5]}: diff {d[bad[:5]]}, norm {nrm[bad[:5]]}")
+    print(f"R rows: max diff/(norm) {np.max(d / np.maximum(nrm, 1e-300)):.2e}, "
+          f"max abs diff {d.max():.2e} (||A||_F {np.linalg.norm(a):.2e})")
+    if pre >= k:
+        # tau_j = 1 - alpha/beta inherits the relative error of column j, which is
+        # about the absolute floor divided by |R_jj|
+        rjj = np.abs(np.diag(r_o)[:k])
+        tol = 1e-10 + 4.0 * floor / np.maximum(rjj, 1e-300)
+        assert np.all(np.abs(tau - ref.tau) <= tol)
+    # the GPU factorization on its own
+    q = q_from_inplace(qr, tau)
+    r_full = np.triu(qr)
+    r_full[k:, k:] = qr[k:, k:]
+    ap = a[:, jpvt]
+    assert np.linalg.norm(ap - q @ r_full) / np.linalg.norm(a) <= 1e-13
+    assert np.linalg.norm(q.T @ q - np.eye(m), 2) <= 1e-13
+    # block T reproduces the block reflectors
+    col0 = 0
+    while col0 < k:
+        bj = min(b, k - col0)
+        tj = T[:bj, col0:col0 + bj]
+        y = oracle.unit_lower(qr[col0:, col0:col0 + bj], bj)
+        np.testing.assert_allclose(tj, oracle.form_t(y, tau[col0:col0 + bj]), atol=1e-12)
+        col0 += bj
+    return pre
+
+
+@pytest.mark.parametrize("m,n,b,p,k", [
+    (300, 240, 32, 8, None),     # several panel tiles, ragged
+    (130, 200, 16, 8, 100),      # partial factorization, wide
+    (257, 129, 8, 0, None),      # p = 0, odd sizes
+    (64, 64, 64, 0, None),       # one block, ell = m
+    (500, 300, 64, 8, 200),
+])
+def test_rqrcp_matches_oracle_small(api, m, n, b, p, k):
+    k = min(m, n) if k is None else k
+    sig = synth.spectrum("pow10", min(m, n), scale=min(m, n) / 6.0)
+    a = synth.low_rank(m, n, sig, 4000 + m, 4001 + n)
+    om = synth.omega(b + p, m, 4002 + m + n)
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, k, a, om)
+    _check_against_oracle(a, om, b, p, k, qr, jpvt, tau, T, min_prefix=min(k, 16))
+
+
+def test_rqrcp_identity_compression_equals_qrcp(api):
+    m, n, b, p = 64, 40, 16, 48
+    a, _ = synth.graded_known_pivots(m, n, 4100, ratio=0.7)
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, n, a, np.eye(m))
+    ref = oracle.qrcp(a, k=n)
+    np.testing.assert_array_equal(jpvt, ref.jpvt)
+
+
+def test_rqrcp_config_1000(api):
+    """1000 x 1000, sigma_i = 10^(-i/100), b = 32, p = 8 (the parity workload)."""
+    cfg = synth.workload(0)
+    m, n, b, p = cfg["m"], cfg["n"], cfg["b"], cfg["p"]
+    sig = synth.spectrum("pow10", n, scale=100.0)
+    a = synth.low_rank(m, n, sig, synth.seed_for(0, "U"), synth.seed_for(0, "V"))
+    om = synth.omega(b + p, m, synth.seed_for(0, "Omega"))
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, n, a, om)
+    pre = _check_against_oracle(a, om, b, p, n, qr, jpvt, tau, T, min_prefix=32)
+    print(f"certified pivot prefix {pre}/{n}")
+
+
+def test_rqrcp_known_pivot_family_full_parity(api):
+    """Steeply graded columns: every sample decision is certified."""
+    m, n, b, p = 200, 120, 16, 8
+    a, _ = synth.graded_known_pivots(m, n, 4200, ratio=0.75, eta=1e-3)
+    om = synth.omega(b + p, m, 4201)
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, n, a, om)
+    _check_against_oracle(a, om, b, p, n, qr, jpvt, tau, T, min_prefix=60)
+
+
+def test_rqrcp_zero_rank_and_empty(api):
+    m, n = 40, 30
+    A = _dev(api, np.zeros((m, n)))
+    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, synth.omega(10, m, 1)), 8, 2, k=0)
+    api.default_handle(0).sync()
+    np.testing.assert_array_equal(_host(jpvt), np.arange(n))
+
+
+def test_rqrcp_deterministic(api):
+    m, n, b, p = 400, 380, 32, 8
+    a = synth.gaussian((m, n), 4300)
+    om = synth.omega(b + p, m, 4301)
+    r1 = _rqrcp_case(api, m, n, b, p, n, a, om)
+    r2 = _rqrcp_case(api, m, n, b, p, n, a, om)
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
