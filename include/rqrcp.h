@@ -205,6 +205,21 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
 rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, double* B,
                          int64_t ldb, int64_t* perm);
 
+/*
+ * Kernel timing for measurement.  Between rq_profile_start and rq_profile_stop
+ * every kernel the handle launches is bracketed by HIP events on the handle's
+ * stream and attributed to a named kernel class together with its algorithmic
+ * flop and byte counts (the work the mathematics needs, not what the hardware
+ * moved).  rq_profile_stop waits for the stream and folds the events into
+ * per-class totals, which rq_profile_get reports (class index 0..count-1).
+ * Errors: -1 null handle, -2 index out of range.
+ */
+rq_status rq_profile_start(rq_handle h);
+rq_status rq_profile_stop(rq_handle h);
+int32_t rq_profile_count(rq_handle h);
+rq_status rq_profile_get(rq_handle h, int32_t index, const char** name, int64_t* launches,
+                         double* total_ms, double* flops, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

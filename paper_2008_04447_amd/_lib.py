@@ -32,6 +32,13 @@ SIGNATURES = {
     "rq_sketch": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
                                    c_i64, c_p, c_i64]),
     "rq_sample_qrcp": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_p, c_i64, c_p]),
+    "rq_profile_start": (ctypes.c_int32, [c_p]),
+    "rq_profile_stop": (ctypes.c_int32, [c_p]),
+    "rq_profile_count": (ctypes.c_int32, [c_p]),
+    "rq_profile_get": (ctypes.c_int32, [c_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p),
+                                        ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
 }
 
 RQ_OK = 0

@@ -1,66 +1,14 @@
 // Host side of the C ABI declared in include/rqrcp.h: handle, argument
-// validation, workspace and the block loops that enqueue the gfx950 kernels.
+// validation, workspace, kernel timing and the RQRCP block loop.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <string>
 
-#include "../../include/rqrcp.h"
-#include "kernels.hpp"
+#include "host.hpp"
 
-struct rq_handle_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;          // grow-only workspace
-  size_t ws_bytes = 0;
-  int64_t* status = nullptr;   // device int64[4]
-  uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag
-  std::string last_error;
-};
-
-namespace {
-
-using rq::launch_zero_u32;
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-rq_status fail(rq_handle h, hipError_t e, const char* where) {
-  if (h) {
-    h->last_error = std::string(where) + ": " + hipGetErrorString(e);
-  }
-  return RQ_E_HIP;
-}
-
-#define RQ_CHECK(h, expr)                              \
-  do {                                                 \
-    hipError_t _e = (expr);                            \
-    if (_e != hipSuccess) return fail((h), _e, #expr); \
-  } while (0)
-
-// Bump allocator over the handle's workspace.  reserve() is called once with
-// the total size before carving, so pointers stay valid for the whole call.
-struct Carve {
-  char* base;
-  size_t off = 0;
-  explicit Carve(char* b) : base(b) {}
-  template <class T>
-  T* take(size_t count) {
-    off = (off + 255) & ~size_t(255);
-    T* p = reinterpret_cast<T*>(base + off);
-    off += count * sizeof(T);
-    return p;
-  }
-};
+namespace rq {
 
 rq_status reserve(rq_handle h, size_t bytes) {
   if (bytes <= h->ws_bytes) return RQ_OK;
@@ -81,17 +29,41 @@ rq_status reserve(rq_handle h, size_t bytes) {
   return RQ_OK;
 }
 
-size_t bytes_of_doubles(size_t n) { return n * sizeof(double) + 256; }
+static hipEvent_t next_event(rq_handle h) {
+  if (h->pool_used < h->pool.size()) return h->pool[h->pool_used++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  h->pool.push_back(e);
+  h->pool_used++;
+  return e;
+}
 
-int panel_groups(int64_t M) { return (int)((M + rq::kPanelRows - 1) / rq::kPanelRows); }
+KTimer::KTimer(rq_handle h_, int cls_, double f_, double b_) : h(h_), cls(cls_), f(f_), b(b_) {
+  if (h->prof) {
+    e0 = next_event(h);
+    if (e0) (void)hipEventRecord(e0, h->stream);
+  }
+}
 
-// Sketch B = Omega A (ell x n) through split-K partials in `part`.
-rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega,
-                      int64_t ldo, const double* A, int64_t lda, double* B, int64_t ldb,
-                      double* part) {
+KTimer::~KTimer() {
+  if (!e0) return;
+  hipEvent_t e1 = next_event(h);
+  if (!e1) return;
+  (void)hipEventRecord(e1, h->stream);
+  h->recs.push_back(ProfRec{cls, e0, e1, f, b});
+}
+
+size_t sketch_part_doubles(int ell, int64_t m, int64_t n) {
   int ks, kc;
-  rq::plan_split((int)m, (int)n, &ks, &kc);
-  rq::GemmArgs g{};
+  plan_split((int)m, (int)n, &ks, &kc);
+  return ks > 1 ? (size_t)ks * ell * n : 0;
+}
+
+rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
+                      const double* A, int64_t lda, double* B, int64_t ldb, double* part) {
+  int ks, kc;
+  plan_split((int)m, (int)n, &ks, &kc);
+  GemmArgs g{};
   g.L = Omega;
   g.sLp = 1;
   g.sLk = ldo;
@@ -104,37 +76,39 @@ rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* 
   g.kchunk = kc;
   g.alpha = 1.0;
   g.beta = 0.0;
+  const double fl = 2.0 * ell * m * n;
+  const double by = 8.0 * ((double)m * n + (double)ell * m + (double)ell * n);
   if (ks == 1) {
     g.out = B;
     g.ldout = ldb;
-    RQ_CHECK(h, rq::launch_gemm_lx(g, h->stream));
+    KTimer kt(h, K_SKETCH, fl, by);
+    RQ_CHECK(h, launch_gemm_lx(g, h->stream));
     return RQ_OK;
   }
   g.out = part;
   g.ldout = ell;
   g.split_stride = (int64_t)ell * n;
-  RQ_CHECK(h, rq::launch_gemm_lx(g, h->stream));
-  RQ_CHECK(h, rq::launch_reduce(part, ell, g.split_stride, ks, ell, (int)n, B, ldb, nullptr, 0,
-                                0, h->stream));
+  {
+    KTimer kt(h, K_SKETCH, fl, by + 8.0 * ks * ell * n);
+    RQ_CHECK(h, launch_gemm_lx(g, h->stream));
+  }
+  {
+    KTimer kt(h, K_REDUCE, (double)(ks - 1) * ell * n, 8.0 * (ks + 1) * ell * n);
+    RQ_CHECK(h, launch_reduce(part, ell, g.split_stride, ks, ell, (int)n, B, ldb, nullptr, 0, 0,
+                              h->stream));
+  }
   return RQ_OK;
 }
 
-size_t sketch_part_doubles(int ell, int64_t m, int64_t n) {
-  int ks, kc;
-  rq::plan_split((int)m, (int)n, &ks, &kc);
-  return ks > 1 ? (size_t)ks * ell * n : 0;
+size_t sq_rec_doubles(int ell, int64_t N) {
+  const int lm = sq_lm(ell);
+  return (size_t)2 * ((N + 255) / 256) * sq_record_stride(lm);
 }
-
-struct SqWork {
-  double* rec;
-  int* src_top;
-  int* dst_low;
-};
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm) {
-  const int lm = rq::sq_lm(ell);
-  rq::SqArgs a{};
+  const int lm = sq_lm(ell);
+  SqArgs a{};
   a.B = B;
   a.ldb = ldb;
   a.ell = ell;
@@ -142,7 +116,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.steps = steps;
   a.nwg = (int)((N + 255) / 256);
   a.rec = w.rec;
-  a.rs = rq::sq_record_stride(lm);
+  a.rs = sq_record_stride(lm);
   a.counter = h->sync;
   a.abort_flag = h->sync + 1;
   a.status = h->status;
@@ -150,18 +124,18 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.dst_low = w.dst_low;
   a.perm = perm;
   RQ_CHECK(h, launch_zero_u32(h->sync, 2, h->stream));
-  RQ_CHECK(h, rq::launch_sample_qrcp(a, lm, h->stream));
+  KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
+  RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
   return RQ_OK;
 }
 
-size_t sq_rec_doubles(int ell, int64_t N) {
-  const int lm = rq::sq_lm(ell);
-  return (size_t)2 * ((N + 255) / 256) * rq::sq_record_stride(lm);
-}
+static int panel_groups(int64_t M) { return (int)((M + kPanelRows - 1) / kPanelRows); }
+
+size_t panel_rec_doubles(int64_t M) { return (size_t)2 * panel_groups(M) * 3 * 64; }
 
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt) {
-  rq::PanelArgs a{};
+  PanelArgs a{};
   a.A = A;
   a.lda = lda;
   a.M = (int)M;
@@ -177,15 +151,44 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
   a.T = T;
   a.ldt = ldt;
   RQ_CHECK(h, launch_zero_u32(h->sync, 2, h->stream));
-  RQ_CHECK(h, rq::launch_panel(a, h->stream));
+  KTimer kt(h, K_PANEL, 2.0 * (double)M * bj * bj, 8.0 * (double)M * (2.0 * bj + 64));
+  RQ_CHECK(h, launch_panel(a, h->stream));
   return RQ_OK;
 }
 
-size_t panel_rec_doubles(int64_t M) { return (size_t)2 * panel_groups(M) * 3 * 64; }
+// B1 = S12 - (S11 R11^{-1}) R12 in place on rows 0..bj-1 of the sample block
+// (columns bj..), B2 = S22 untouched (eq. update1).
+rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
+                            const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat) {
+  {
+    KTimer kt(h, K_OMEGA11, (double)bj * bj * bj / 3.0, 8.0 * 2 * bj * bj);
+    RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, h->stream));
+  }
+  GemmArgs u{};
+  u.L = mhat;
+  u.sLp = 1;
+  u.sLk = 64;
+  u.X = R12;
+  u.ldx = ldr12;
+  u.P = bj;
+  u.K = bj;
+  u.N = (int)Nt;
+  u.ksplit = 1;
+  u.kchunk = ((bj + 15) / 16) * 16;
+  u.out = sblk + (int64_t)bj * ell;
+  u.ldout = ell;
+  u.alpha = -1.0;
+  u.beta = 1.0;
+  u.C = sblk + (int64_t)bj * ell;
+  u.ldc = ell;
+  KTimer kt(h, K_SAMPLE_UPDATE, 2.0 * bj * bj * (double)Nt, 8.0 * 3.0 * bj * (double)Nt);
+  RQ_CHECK(h, launch_gemm_lx(u, h->stream));
+  return RQ_OK;
+}
 
-bool valid_ptr(const void* p, int64_t count) { return count <= 0 || p != nullptr; }
+}  // namespace rq
 
-}  // namespace
+using namespace rq;
 
 extern "C" {
 
@@ -216,6 +219,7 @@ rq_status rq_destroy(rq_handle h) {
   if (!h) return -1;
   DeviceGuard guard(h->device);
   (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->status) (void)hipFree(h->status);
   if (h->sync) (void)hipFree(h->sync);
@@ -237,11 +241,52 @@ rq_status rq_sync_status(rq_handle h, int64_t* device_error) {
   RQ_CHECK(h, hipStreamSynchronize(h->stream));
   int64_t st[4] = {0, 0, 0, 0};
   RQ_CHECK(h, hipMemcpy(st, h->status, sizeof(st), hipMemcpyDeviceToHost));
-  if (st[0]) {
-    RQ_CHECK(h, hipMemset(h->status, 0, 4 * sizeof(int64_t)));
-  }
+  if (st[0]) RQ_CHECK(h, hipMemset(h->status, 0, 4 * sizeof(int64_t)));
   if (device_error) *device_error = st[0];
   return st[0] ? RQ_E_DEVICE : RQ_OK;
+}
+
+rq_status rq_profile_start(rq_handle h) {
+  if (!h) return -1;
+  h->prof = true;
+  h->recs.clear();
+  h->pool_used = 0;
+  for (auto& t : h->tot) t = ProfTot{};
+  return RQ_OK;
+}
+
+rq_status rq_profile_stop(rq_handle h) {
+  if (!h) return -1;
+  DeviceGuard guard(h->device);
+  RQ_CHECK(h, hipStreamSynchronize(h->stream));
+  for (const ProfRec& r : h->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
+    ProfTot& t = h->tot[r.cls];
+    t.launches += 1;
+    t.ms += ms;
+    t.flops += r.flops;
+    t.bytes += r.bytes;
+  }
+  h->recs.clear();
+  h->pool_used = 0;
+  h->prof = false;
+  return RQ_OK;
+}
+
+int32_t rq_profile_count(rq_handle h) { return h ? (int32_t)K_NUM_CLASSES : 0; }
+
+rq_status rq_profile_get(rq_handle h, int32_t index, const char** name, int64_t* launches,
+                         double* total_ms, double* flops, double* bytes) {
+  if (!h) return -1;
+  if (index < 0 || index >= K_NUM_CLASSES) return -2;
+  const ProfTot& t = h->tot[index];
+  if (name) *name = kclass_name(index);
+  if (launches) *launches = t.launches;
+  if (total_ms) *total_ms = t.ms;
+  if (flops) *flops = t.flops;
+  if (bytes) *bytes = t.bytes;
+  return RQ_OK;
 }
 
 rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n,
@@ -261,11 +306,10 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
   if (prec != RQ_FP64) return RQ_E_UNSUPPORTED;
   if (n == 0) return RQ_OK;
   DeviceGuard guard(h->device);
-  size_t need = bytes_of_doubles(sketch_part_doubles((int)ell, m, n));
-  rq_status st = reserve(h, need);
-  if (st) return st;
+  const size_t np = sketch_part_doubles((int)ell, m, n);
+  RQ_TRY(reserve(h, padded_bytes(np)));
   Carve cv(h->ws);
-  double* part = cv.take<double>(sketch_part_doubles((int)ell, m, n));
+  double* part = cv.take<double>(np);
   return sketch_fp64(h, (int)ell, m, n, Omega, ldo, static_cast<const double*>(A), lda, B, ldb,
                      part);
 }
@@ -281,16 +325,14 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
   if (!valid_ptr(perm, n)) return -7;
   if (n == 0) return RQ_OK;
   DeviceGuard guard(h->device);
-  size_t need = bytes_of_doubles(sq_rec_doubles((int)ell, n)) + 2 * 64 * sizeof(int) + 512;
-  rq_status st = reserve(h, need);
-  if (st) return st;
+  RQ_TRY(reserve(h, padded_bytes(sq_rec_doubles((int)ell, n)) + 2 * 64 * sizeof(int) + 512));
   Carve cv(h->ws);
   SqWork w;
   w.rec = cv.take<double>(sq_rec_doubles((int)ell, n));
   w.src_top = cv.take<int>(64);
   w.dst_low = cv.take<int>(64);
   if (steps == 0) {
-    RQ_CHECK(h, rq::launch_iota(perm, (int)n, h->stream));
+    RQ_CHECK(h, launch_iota(perm, (int)n, h->stream));
     return RQ_OK;
   }
   return run_sample_qrcp(h, B, ldb, (int)ell, n, (int)steps, w, perm);
@@ -316,8 +358,9 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   if (T && ldt < b) return -14;
   if (n == 0) return RQ_OK;
   DeviceGuard guard(h->device);
+  hipStream_t s = h->stream;
   if (k == 0) {
-    RQ_CHECK(h, rq::launch_iota(jpvt, (int)n, h->stream));
+    RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
     return RQ_OK;
   }
 
@@ -327,7 +370,7 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     const int64_t nt = n - c0 - std::min<int64_t>(b, k - c0);
     if (nt <= 0) continue;
     int ks_b, kc_b;
-    rq::plan_split((int)(m - c0), (int)nt, &ks_b, &kc_b);
+    plan_split((int)(m - c0), (int)nt, &ks_b, &kc_b);
     w_part = std::max(w_part, (size_t)ks_b * 64 * nt);
   }
   const size_t n_sample = (size_t)ell * n;
@@ -335,12 +378,10 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   const size_t n_sqrec = sq_rec_doubles((int)ell, n);
   const size_t n_prec = panel_rec_doubles(m);
   const size_t n_y = (size_t)m * 64;
-  const size_t need = bytes_of_doubles(n_sample) + bytes_of_doubles(n_part) +
-                      bytes_of_doubles(n_sqrec) + bytes_of_doubles(n_prec) +
-                      bytes_of_doubles(n_y) + bytes_of_doubles(64 * 64) * 2 +
-                      bytes_of_doubles((size_t)64 * n) + 4 * 64 * sizeof(int) + 1024;
-  rq_status st = reserve(h, need);
-  if (st) return st;
+  const size_t need = padded_bytes(n_sample) + padded_bytes(n_part) + padded_bytes(n_sqrec) +
+                      padded_bytes(n_prec) + padded_bytes(n_y) + 2 * padded_bytes(64 * 64) +
+                      padded_bytes((size_t)64 * n) + 4 * 64 * sizeof(int) + 1024;
+  RQ_TRY(reserve(h, need));
   Carve cv(h->ws);
   double* sample = cv.take<double>(n_sample);
   double* part = cv.take<double>(n_part);
@@ -353,35 +394,37 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   double* zbuf = cv.take<double>((size_t)64 * n);
   sw.src_top = cv.take<int>(64);
   sw.dst_low = cv.take<int>(64);
-  hipStream_t s = h->stream;
 
   // ---- B = Omega A -------------------------------------------------------------
-  st = sketch_fp64(h, (int)ell, m, n, Omega, ldo, A, lda, sample, ell, part);
-  if (st) return st;
-  RQ_CHECK(h, rq::launch_iota(jpvt, (int)n, s));
+  RQ_TRY(sketch_fp64(h, (int)ell, m, n, Omega, ldo, A, lda, sample, ell, part));
+  RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
 
   for (int64_t col0 = 0; col0 < k; col0 += b) {
     const int bj = (int)std::min<int64_t>(b, k - col0);
     const int64_t N = n - col0;
     const int64_t M = m - col0;
     double* Ablk = A + col0 + col0 * lda;            // trailing block A(col0:, col0:)
-    // 1. sample pivots (QRCP(B, b)); the sample is rewritten in pivoted order
-    st = run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr);
-    if (st) return st;
-    // 2. permute all m rows of A's columns col0.. (finished R rows included) and jpvt
-    RQ_CHECK(h, rq::launch_permute(A + col0 * lda, lda, (int)m, bj, sw.src_top, sw.dst_low,
-                                   jpvt + col0, s));
-    // 3. panel QR of the b selected columns, T of the block
-    st = run_panel(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tblk, 64);
-    if (st) return st;
-    if (T) RQ_CHECK(h, rq::launch_copy2d(tblk, 64, T + col0 * ldt, ldt, bj, bj, s));
+    // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
+    RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr));
+    // 2. permute all m rows of A's columns col0.. (finished R rows included), jpvt
+    {
+      KTimer kt(h, K_PERMUTE, 0.0, 32.0 * bj * (double)m);
+      RQ_CHECK(h, launch_permute(A + col0 * lda, lda, (int)m, bj, sw.src_top, sw.dst_low,
+                                 jpvt + col0, s));
+    }
+    // 3. panel QR of the b selected columns and T of the block
+    RQ_TRY(run_panel(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tblk, 64));
+    if (T) {
+      KTimer kt(h, K_OTHER, 0.0, 16.0 * bj * bj);
+      RQ_CHECK(h, launch_copy2d(tblk, 64, T + col0 * ldt, ldt, bj, bj, s));
+    }
     const int64_t Nt = N - bj;
     if (Nt <= 0) continue;
     double* Ctr = Ablk + bj * lda;                   // A(col0:, col0+bj:)
-    // 4. W = Y^T A_trailing (split-K), Z = T^T W
+    // 4. W = Y^T A_trailing (split-K partials), Z = T^T W
     int ks, kc;
-    rq::plan_split((int)M, (int)Nt, &ks, &kc);
-    rq::GemmArgs g{};
+    plan_split((int)M, (int)Nt, &ks, &kc);
+    GemmArgs g{};
     g.L = ybuf;
     g.sLp = m;
     g.sLk = 1;
@@ -392,69 +435,34 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     g.N = (int)Nt;
     g.ksplit = ks;
     g.kchunk = kc;
-    g.out = part;
+    g.out = part;                                    // ksplit == 1 lands here too
     g.ldout = 64;
     g.split_stride = (int64_t)64 * Nt;
     g.alpha = 1.0;
     g.beta = 0.0;
-    // with ksplit == 1 the single product lands in `part` too (alpha=1, beta=0)
-    RQ_CHECK(h, rq::launch_gemm_lx(g, s));
-    RQ_CHECK(h, rq::launch_reduce(part, 64, g.split_stride, ks, bj, (int)Nt, zbuf, 64, tblk, 64,
-                                  bj, s));
-    // 5. A_trailing -= Y Z  (rows 0..bj-1 become R12)
-    RQ_CHECK(h, rq::launch_update(Ctr, lda, (int)M, (int)Nt, ybuf, m, zbuf, 64, bj, s));
-    // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
-    if (col0 + bj < k) {
-      double* sblk = sample + col0 * ell;
-      RQ_CHECK(h, rq::launch_omega11(sblk, ell, Ablk, lda, bj, mhat, 64, s));
-      rq::GemmArgs u{};
-      u.L = mhat;
-      u.sLp = 1;
-      u.sLk = 64;
-      u.X = Ctr;
-      u.ldx = lda;
-      u.P = bj;
-      u.K = bj;
-      u.N = (int)Nt;
-      u.ksplit = 1;
-      u.kchunk = ((bj + 15) / 16) * 16;
-      u.out = sblk + bj * ell;
-      u.ldout = ell;
-      u.alpha = -1.0;
-      u.beta = 1.0;
-      u.C = sblk + bj * ell;
-      u.ldc = ell;
-      RQ_CHECK(h, rq::launch_gemm_lx(u, s));
+    {
+      KTimer kt(h, K_INNER, 2.0 * bj * (double)M * Nt,
+                8.0 * ((double)M * Nt + (double)M * bj + (double)ks * bj * Nt));
+      RQ_CHECK(h, launch_gemm_lx(g, s));
     }
+    {
+      KTimer kt(h, K_REDUCE, (double)bj * bj * Nt + (double)(ks - 1) * bj * Nt,
+                8.0 * ((double)ks * bj * Nt + 64.0 * Nt));
+      RQ_CHECK(h, launch_reduce(part, 64, g.split_stride, ks, bj, (int)Nt, zbuf, 64, tblk, 64,
+                                bj, s));
+    }
+    // 5. A_trailing -= Y Z (rows 0..bj-1 become R12)
+    {
+      KTimer kt(h, K_UPDATE, 2.0 * bj * (double)M * Nt,
+                8.0 * (2.0 * M * Nt + (double)M * bj + (double)bj * Nt));
+      RQ_CHECK(h, launch_update(Ctr, lda, (int)M, (int)Nt, ybuf, m, zbuf, 64, bj, s));
+    }
+    // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
+    if (col0 + bj < k)
+      RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
+                               mhat));
   }
   return RQ_OK;
-}
-
-rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t nb, double* A,
-                      int64_t lda, int64_t* jpvt, double* tau) {
-  if (!h) return -1;
-  (void)m; (void)n; (void)k; (void)nb; (void)A; (void)lda; (void)jpvt; (void)tau;
-  return RQ_E_UNSUPPORTED;
-}
-
-rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
-                          int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
-                          int64_t* jpvt, double* Y, int64_t ldy, double* T, int64_t ldt,
-                          double* R, int64_t ldr) {
-  if (!h) return -1;
-  (void)prec; (void)m; (void)n; (void)k; (void)b; (void)p; (void)A; (void)lda; (void)Omega;
-  (void)ldo; (void)jpvt; (void)Y; (void)ldy; (void)T; (void)ldt; (void)R; (void)ldr;
-  return RQ_E_UNSUPPORTED;
-}
-
-rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
-                   int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
-                   double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
-                   int64_t* jpvt) {
-  if (!h) return -1;
-  (void)prec; (void)m; (void)n; (void)k; (void)b; (void)p; (void)A; (void)lda; (void)Omega;
-  (void)ldo; (void)U; (void)ldu; (void)X; (void)ldx; (void)V; (void)ldv; (void)jpvt;
-  return RQ_E_UNSUPPORTED;
 }
 
 }  // extern "C"

@@ -119,33 +119,32 @@ __global__ __launch_bounds__(256) void reduce_plain_kernel(const double* part, i
   out[p + n * ldout] = s;
 }
 
+// Four columns per workgroup, one thread per (row i, column): the split-K
+// partials of a column are summed into LDS by 64 threads, then row i of
+// Z = T^T W is an inner product of column i of T with that column.
 __global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64_t ldp,
                                                        int64_t sstride, int ks, int N,
                                                        double* Z, const double* T, int64_t ldt,
                                                        int bj) {
   __shared__ double s_T[64][65];
+  __shared__ double s_w[4][64];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int i = e % 64, q = e / 64;
     s_T[i][q] = (i < bj && q < bj && i <= q) ? T[i + (int64_t)q * ldt] : 0.0;
   }
+  const int i = threadIdx.x & 63;
+  const int cl = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 4 + cl;
+  double w = 0.0;
+  if (n < N && i < bj)
+    for (int r = 0; r < ks; ++r) w += part[r * sstride + i + n * ldp];
+  s_w[cl][i] = w;
   __syncthreads();
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
-  double w[64];
-#pragma unroll
-  for (int q = 0; q < 64; ++q) {
-    double s = 0.0;
-    if (q < bj)
-      for (int r = 0; r < ks; ++r) s += part[r * sstride + q + n * ldp];
-    w[q] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    double z = 0.0;
-#pragma unroll
-    for (int q = 0; q <= i; ++q) z += s_T[q][i] * w[q];
-    Z[i + n * 64] = (i < bj) ? z : 0.0;
-  }
+  double z = 0.0;
+#pragma unroll 16
+  for (int q = 0; q < 64; ++q) z += s_T[q][i] * s_w[cl][q];
+  Z[i + n * 64] = (i < bj) ? z : 0.0;
 }
 
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P, int N,
@@ -153,8 +152,8 @@ hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int k
                          hipStream_t s) {
   if (N <= 0) return hipSuccess;
   if (T) {
-    hipLaunchKernelGGL(reduce_t_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, ldp,
-                       sstride, ks, N, out, T, ldt, bj);
+    hipLaunchKernelGGL(reduce_t_kernel, dim3((N + 3) / 4), dim3(256), 0, s, part, ldp, sstride,
+                       ks, N, out, T, ldt, bj);
   } else {
     const int64_t total = (int64_t)P * N;
     hipLaunchKernelGGL(reduce_plain_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,

@@ -25,21 +25,24 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 // Cross-workgroup barrier for persistent kernels whose workgroups are all
 // resident.  `counter` starts at 0 for the launch; barrier number `idx`
 // (0-based) completes when the counter reaches nwg * (idx + 1).  Every
-// workgroup calls it the same number of times.  Returns false when the wait
-// timed out or another workgroup aborted; the caller must then leave the
-// kernel.  All threads of the workgroup must call it.
+// workgroup calls it the same number of times with all of its threads.
+// The workgroup first synchronizes internally (which orders its threads'
+// global writes before thread 0's), then thread 0 alone performs the
+// device-scope release, the arrival and the bounded wait, and one device-scope
+// acquire before the workgroup proceeds.  With a single workgroup the internal
+// synchronization is all that is needed.  Returns false when the wait timed out
+// or another workgroup aborted; the caller must then leave the kernel.
 RQ_DEV bool grid_barrier(uint32_t* counter, uint32_t* abort_flag, uint32_t nwg, uint32_t idx,
                          int64_t* status) {
   __shared__ int s_ok;
-  // make this thread's global writes visible at device scope before arriving
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
+  if (nwg == 1) return true;
   if (threadIdx.x == 0) {
     const uint32_t target = nwg * (idx + 1u);
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     uint32_t it = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         ok = 0;
         break;
@@ -50,13 +53,13 @@ RQ_DEV bool grid_barrier(uint32_t* counter, uint32_t* abort_flag, uint32_t nwg, 
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
+    // later loads of data published by other workgroups must not hit stale lines
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
-  // later loads of data published by other workgroups must not hit stale lines
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return s_ok != 0;
 }
 

@@ -1,0 +1,147 @@
+// Host-side internals shared by the entry points: the handle, error plumbing,
+// the workspace carve-out and event-based kernel timing.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rqrcp.h"
+#include "kernels.hpp"
+
+namespace rq {
+
+// Kernel classes reported by rq_profile_get.
+enum KClass {
+  K_SKETCH = 0,
+  K_SAMPLE_QRCP,
+  K_PERMUTE,
+  K_PANEL,
+  K_INNER,          // W = Y^T A (split-K)
+  K_REDUCE,         // fixed-order split-K sum (and T^T W)
+  K_UPDATE,         // A -= Y Z
+  K_OMEGA11,
+  K_SAMPLE_UPDATE,
+  K_QP3_PIVOT,      // plain QRCP: argmax, swap, column update, reflector
+  K_QP3_GEMV,       // plain QRCP: adjusted inner products over the trailing matrix
+  K_QP3_ROW,        // plain QRCP: row update and norm downdate
+  K_TR_SELECT,      // TRQRCP: selected columns A - Y W^T
+  K_TR_ROWS,        // TRQRCP: new R rows A - Y W^T
+  K_TR_SMALL,       // TRQRCP/TUXV: small products (Y2^T Y, T composition, ...)
+  K_OTHER,
+  K_NUM_CLASSES
+};
+
+inline const char* kclass_name(int c) {
+  static const char* names[K_NUM_CLASSES] = {
+      "sketch", "sample_qrcp", "permute", "panel", "inner_products", "reduce",
+      "trailing_update", "omega11", "sample_update", "qp3_pivot", "qp3_gemv", "qp3_row",
+      "tr_select", "tr_rows", "tr_small", "other"};
+  return (c >= 0 && c < K_NUM_CLASSES) ? names[c] : "?";
+}
+
+struct ProfRec {
+  int cls;
+  hipEvent_t e0, e1;
+  double flops, bytes;
+};
+struct ProfTot {
+  int64_t launches = 0;
+  double ms = 0, flops = 0, bytes = 0;
+};
+
+}  // namespace rq
+
+struct rq_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;          // grow-only workspace
+  size_t ws_bytes = 0;
+  int64_t* status = nullptr;   // device int64[4]
+  uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag
+  std::string last_error;
+  bool prof = false;
+  std::vector<rq::ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  rq::ProfTot tot[rq::K_NUM_CLASSES];
+};
+
+namespace rq {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+inline rq_status fail(rq_handle h, hipError_t e, const char* where) {
+  if (h) h->last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return RQ_E_HIP;
+}
+
+#define RQ_CHECK(h, expr)                                  \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return rq::fail((h), _e, #expr); \
+  } while (0)
+
+#define RQ_TRY(expr)              \
+  do {                            \
+    rq_status _s = (expr);        \
+    if (_s != RQ_OK) return _s;   \
+  } while (0)
+
+// Bump allocator over the handle's workspace (reserve() first).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(char* b) : base(b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+inline size_t padded_bytes(size_t n_doubles) { return n_doubles * sizeof(double) + 256; }
+
+rq_status reserve(rq_handle h, size_t bytes);
+
+// Brackets the launches in its scope with events when profiling is on.
+struct KTimer {
+  rq_handle h;
+  int cls;
+  double f, b;
+  hipEvent_t e0 = nullptr;
+  KTimer(rq_handle h_, int cls_, double f_, double b_);
+  ~KTimer();
+};
+
+inline bool valid_ptr(const void* p, int64_t count) { return count <= 0 || p != nullptr; }
+
+// Shared building blocks of the block loops (api.hip).
+struct SqWork {
+  double* rec;
+  int* src_top;
+  int* dst_low;
+};
+size_t sq_rec_doubles(int ell, int64_t N);
+size_t panel_rec_doubles(int64_t M);
+size_t sketch_part_doubles(int ell, int64_t m, int64_t n);
+rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
+                      const double* A, int64_t lda, double* B, int64_t ldb, double* part);
+rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
+                          SqWork w, int64_t* perm);
+rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
+                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt);
+rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
+                            const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat);
+
+}  // namespace rq

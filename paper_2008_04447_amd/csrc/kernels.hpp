@@ -21,6 +21,7 @@ struct SqArgs {
 };
 int sq_lm(int ell);    // padded register height used for a given ell (0 = unsupported)
 int sq_record_stride(int lm);
+int sq_columns_per_group();   // sample columns held by one workgroup
 hipError_t launch_sample_qrcp(const SqArgs& a, int lm, hipStream_t s);
 
 // ---- panel Householder QR + compact-WY T (persistent) ----------------------

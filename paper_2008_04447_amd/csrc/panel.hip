@@ -2,8 +2,8 @@
 // compact-WY matrix T built on the fly (Section 2.1: Q = I - Y T Y^T).
 //
 // The panel is split by rows over ceil(M / 256) workgroups and held in
-// registers: thread (c, g) of a workgroup owns column c and a contiguous run of
-// 256 * 64 / (256 * 64 / 64) = 64 rows (for bj <= 64, 4 row groups of 64 rows).
+// registers: thread (c, g) of a 1024-thread workgroup owns column c (< 64) and
+// a contiguous run of 16 rows (16 row groups, one per wave).
 // Reflector j needs one reduction over all rows.  Instead of a norm followed by
 // a second pass for v^T a_c, each workgroup reduces the Gram row a_j^T a_c and
 // the row-j entries a_c(j); from these every workgroup derives
@@ -17,10 +17,10 @@
 
 namespace rq {
 
-constexpr int kPanelThreads = 256;
+constexpr int kPanelThreads = 1024;
 constexpr int kPC = 64;                                  // max panel columns
 constexpr int kPG = kPanelThreads / kPC;                 // row groups
-constexpr int kPR = kPanelRows / kPG;                    // rows per thread (64)
+constexpr int kPR = kPanelRows / kPG;                    // rows per thread (16)
 
 __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   const int t = threadIdx.x;
@@ -92,28 +92,48 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
       rec[t] = s;
     }
     if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, (uint32_t)j, a.status)) return;
-    // ---- combine in fixed workgroup order ------------------------------------
+    // ---- combine in a fixed order: 4 interleaved partial sums over workgroups,
+    // every thread keeping several independent loads in flight -----------------
     const double* rj = a.rec + (int64_t)(j & 1) * a.nwg * (3 * kPC);
+    {
+      const int q = t & (kPC - 1), part = t / kPC;
+      double sg = 0.0, sp = 0.0;
+      if (wg == 0) {
+#pragma unroll 8
+        for (int w = part; w < a.nwg; w += kPG) {
+          sg += rj[(int64_t)w * 3 * kPC + q];
+          sp += rj[(int64_t)w * 3 * kPC + 2 * kPC + q];
+        }
+      } else {
+#pragma unroll 8
+        for (int w = part; w < a.nwg; w += kPG) sg += rj[(int64_t)w * 3 * kPC + q];
+      }
+      s_red[part][q] = sg;
+      s_red[part][2 * kPC + q] = sp;
+      if (t < kPC) {
+        const int owner = j / kPanelRows;          // workgroup holding row j
+        s_top[t] = (j < bj && owner < a.nwg) ? rj[(int64_t)owner * 3 * kPC + kPC + t] : 0.0;
+      }
+    }
+    __syncthreads();
     if (t < kPC) {
-      double s = 0.0;
-      for (int w = 0; w < a.nwg; ++w) s += rj[(int64_t)w * 3 * kPC + t];
-      s_G[t] = s;
-    } else if (t < 2 * kPC) {
-      const int owner = j / kPanelRows;            // workgroup holding row j
-      s_top[t - kPC] = (j < bj && owner < a.nwg) ? rj[(int64_t)owner * 3 * kPC + t] : 0.0;
-    } else if (t < 3 * kPC && wg == 0) {
-      double s = 0.0;
-      for (int w = 0; w < a.nwg; ++w) s += rj[(int64_t)w * 3 * kPC + t];
-      s_p[t - 2 * kPC] = s;
+      double g0 = 0.0, p0 = 0.0;
+      for (int q = 0; q < kPG; ++q) {
+        g0 += s_red[q][t];
+        p0 += s_red[q][2 * kPC + t];
+      }
+      s_G[t] = g0;
+      s_p[t] = p0;
     }
     __syncthreads();
     // ---- T column j-1 (workgroup 0) -------------------------------------------
     if (wg == 0 && j >= 1 && t < kPC) {
       const int jc = j - 1;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < kPC; ++q) acc += (q >= t && q < jc) ? s_T[t][q] * s_p[q] : 0.0;
       if (t < jc) {
-        double s = 0.0;
-        for (int q = t; q < jc; ++q) s += s_T[t][q] * s_p[q];
-        s_T[t][jc] = -s_tau[jc] * s;
+        s_T[t][jc] = -s_tau[jc] * acc;
       } else if (t == jc) {
         s_T[jc][jc] = s_tau[jc];
       }

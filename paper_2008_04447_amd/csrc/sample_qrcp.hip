@@ -1,8 +1,9 @@
 // Partial QRCP of the (b+p) x N sample (the pivot block of Algorithms 3-5).
 //
-// Each of the N sample columns lives in the registers of one lane for the whole
-// kernel (ell <= 96 values, padded with zero rows).  A pivot step needs the
-// column of largest trailing 2-norm over all workgroups, so every step ends
+// Each sample column is held in registers by a quad of 4 lanes for the whole
+// kernel (lane q of the quad keeps rows q, q+4, q+8, ...; ell <= 96, padded
+// with zero rows), 256 columns per 1024-thread workgroup.  A pivot step needs
+// the column of largest trailing 2-norm over all workgroups, so every step ends
 // with one cross-workgroup exchange: each workgroup publishes its best
 // (norm^2, position) and that column's values; after the barrier every
 // workgroup picks the same winner, forms the same Householder vector from the
@@ -14,43 +15,69 @@
 
 namespace rq {
 
-constexpr int kSqThreads = 256;
+constexpr int kSqThreads = 1024;
+constexpr int kQ = 4;                          // lanes per column
+constexpr int kSqCols = kSqThreads / kQ;       // columns per workgroup
+constexpr int kSqWaves = kSqThreads / 64;
+constexpr int kSpecCap = 8192;                 // doubles of LDS for the one-round candidate fetch
+
+// Sum over the 4 lanes of a quad; every lane of the quad gets the same bits.
+RQ_DEV double quad_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
 
 template <int LM>
 __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
+  constexpr int RPL = LM / kQ;                 // rows per lane
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
+  const int q = t & (kQ - 1);
+  const int cl = t / kQ;                       // local column
   const int wg = blockIdx.x;
-  const int c = wg * kSqThreads + t;   // input position of the owned column
+  const int c = wg * kSqCols + cl;             // input position of the owned column
   const bool own = c < a.N;
   if (prior_timeout(a.status)) return;
 
   __shared__ double s_v[LM];
   __shared__ double s_col[LM];
-  __shared__ double s_wv[4];
-  __shared__ int s_wp[4], s_ww[4];
-  __shared__ double s_cv[kSqThreads];
-  __shared__ int s_cp[kSqThreads];
+  __shared__ double s_wv[kSqWaves];
+  __shared__ int s_wp[kSqWaves], s_ww[kSqWaves];
+  __shared__ double s_all[kSpecCap];
   __shared__ double s_tau, s_beta, s_best;
   __shared__ int s_owner, s_bestpos, s_winwg, s_winpos;
 
-  double x[LM];
+  double x[RPL];
 #pragma unroll
-  for (int r = 0; r < LM; ++r) x[r] = (own && r < a.ell) ? a.B[r + (int64_t)c * a.ldb] : 0.0;
-  double nu2 = 0.0;
+  for (int i = 0; i < RPL; ++i) {
+    const int r = q + kQ * i;
+    x[i] = (own && r < a.ell) ? a.B[r + (int64_t)c * a.ldb] : 0.0;
+  }
+  double nu2;
+  {
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-  for (int r = 0; r < LM; ++r) nu2 += x[r] * x[r];
+    for (int i = 0; i < RPL; ++i) {
+      if (i & 1)
+        s1 += x[i] * x[i];
+      else
+        s0 += x[i] * x[i];
+    }
+    nu2 = quad_sum(s0 + s1);
+  }
   int pos = own ? c : INT_MAX;
   bool active = own;
   bool flagged = false;
 
   for (int j = 0; j < a.steps; ++j) {
     // ---- local best candidate --------------------------------------------
-    double bv = active ? nu2 : -1.0;
-    int bp = active ? pos : INT_MAX;
-    int who = t;
-    if (active && !flagged && !(nu2 <= 1.7976931348623157e308)) {
+    const bool lead = active && q == 0;
+    double bv = lead ? nu2 : -1.0;
+    int bp = lead ? pos : INT_MAX;
+    int who = cl;
+    if (lead && !flagged && !(nu2 <= 1.7976931348623157e308)) {
       raise_status(a.status, kErrNonFinite);
       flagged = true;
     }
@@ -64,20 +91,20 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
     if (t == 0) {
       double v = s_wv[0];
       int p = s_wp[0], w = s_ww[0];
-      for (int q = 1; q < 4; ++q)
-        if (better(s_wv[q], s_wp[q], v, p)) {
-          v = s_wv[q];
-          p = s_wp[q];
-          w = s_ww[q];
+      for (int k = 1; k < kSqWaves; ++k)
+        if (better(s_wv[k], s_wp[k], v, p)) {
+          v = s_wv[k];
+          p = s_wp[k];
+          w = s_ww[k];
         }
       s_best = v;
       s_bestpos = p;
       s_owner = (p == INT_MAX) ? -1 : w;
     }
     __syncthreads();
-    if (t == s_owner) {
+    if (cl == s_owner) {
 #pragma unroll
-      for (int r = 0; r < LM; ++r) s_col[r] = x[r];
+      for (int i = 0; i < RPL; ++i) s_col[q + kQ * i] = x[i];
     }
     __syncthreads();
     double* rec = a.rec + ((int64_t)(j & 1) * a.nwg + wg) * a.rs;
@@ -89,24 +116,32 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
     // ---- exchange ----------------------------------------------------------
     if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, (uint32_t)j, a.status)) return;
     const double* rj = a.rec + (int64_t)(j & 1) * a.nwg * a.rs;
-    if (t < a.nwg) {
-      s_cv[t] = rj[(int64_t)t * a.rs];
-      s_cp[t] = (int)rj[(int64_t)t * a.rs + 1];
+    // all candidates (value, position) and, when they fit in LDS, their columns,
+    // fetched in one round of independent loads
+    const bool spec = a.nwg * (LM + 2) <= kSpecCap;
+    if (spec) {
+      const int per = LM + 2;
+      for (int e = t; e < a.nwg * per; e += kSqThreads) {
+        const int w = e / per, f = e - w * per;
+        s_all[e] = rj[(int64_t)w * a.rs + f];
+      }
     } else {
-      s_cv[t] = -1.0;
-      s_cp[t] = INT_MAX;
+      for (int w = t; w < a.nwg; w += kSqThreads) {
+        s_all[2 * w] = rj[(int64_t)w * a.rs];
+        s_all[2 * w + 1] = rj[(int64_t)w * a.rs + 1];
+      }
     }
     __syncthreads();
     if (wave == 0) {
-      double v = s_cv[lane];
-      int p = s_cp[lane];
-      int w = lane;
-#pragma unroll
-      for (int q = 1; q < kSqThreads / 64; ++q) {
-        const int i = lane + 64 * q;
-        if (better(s_cv[i], s_cp[i], v, p)) {
-          v = s_cv[i];
-          p = s_cp[i];
+      const int per = spec ? LM + 2 : 2;
+      double v = -1.0;
+      int p = INT_MAX, w = 0;
+      for (int i = lane; i < a.nwg; i += 64) {
+        const double vi = s_all[i * per];
+        const int pi = (int)s_all[i * per + 1];
+        if (better(vi, pi, v, p)) {
+          v = vi;
+          p = pi;
           w = i;
         }
       }
@@ -122,7 +157,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       if (t == 0 && wg == 0) raise_status(a.status, kErrNoPivot);
       return;
     }
-    if (t < LM) s_col[t] = rj[(int64_t)s_winwg * a.rs + 2 + t];
+    if (t < LM)
+      s_col[t] = spec ? s_all[s_winwg * (LM + 2) + 2 + t] : rj[(int64_t)s_winwg * a.rs + 2 + t];
     __syncthreads();
     // ---- Householder vector of the winner (wave 0) ----------------------------
     if (wave == 0) {
@@ -153,24 +189,38 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
         pos = j;
         active = false;
 #pragma unroll
-        for (int r = 0; r < LM; ++r) x[r] = (r < j) ? x[r] : (r == j ? beta : 0.0);
+        for (int i = 0; i < RPL; ++i) {
+          const int r = q + kQ * i;
+          x[i] = (r < j) ? x[i] : (r == j ? beta : 0.0);
+        }
       } else if (pos == j) {
         pos = wpos;
       }
     }
     // ---- apply the reflection to the remaining columns ---------------------------
     if (active) {
-      double d = 0.0;
+      double v[RPL];
+      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < LM; ++r) d += s_v[r] * x[r];
-      d *= tau;
-      // re-read v from LDS rather than keeping a second LM-long register copy
-      const volatile double* vv = s_v;
+      for (int i = 0; i < RPL; ++i) {
+        v[i] = s_v[q + kQ * i];
+        if (i & 1)
+          d1 += v[i] * x[i];
+        else
+          d0 += v[i] * x[i];
+      }
+      const double d = tau * quad_sum(d0 + d1);
+      double n0 = 0.0, n1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < LM; ++r) x[r] -= d * vv[r];
-      nu2 = 0.0;
-#pragma unroll
-      for (int r = 0; r < LM; ++r) nu2 += (r > j) ? x[r] * x[r] : 0.0;
+      for (int i = 0; i < RPL; ++i) {
+        x[i] -= d * v[i];
+        const double sq = (q + kQ * i > j) ? x[i] * x[i] : 0.0;
+        if (i & 1)
+          n1 += sq;
+        else
+          n0 += sq;
+      }
+      nu2 = quad_sum(n0 + n1);
     }
     __syncthreads();   // s_v / s_col are rewritten in the next step
   }
@@ -178,11 +228,15 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   // in-place write of the permuted sample cannot overwrite unread input.
   if (own) {
 #pragma unroll
-    for (int r = 0; r < LM; ++r)
-      if (r < a.ell) a.B[r + (int64_t)pos * a.ldb] = x[r];
-    if (a.src_top && pos < a.steps) a.src_top[pos] = c;
-    if (a.dst_low && c < a.steps) a.dst_low[c] = (pos >= a.steps) ? pos : -1;
-    if (a.perm) a.perm[pos] = c;
+    for (int i = 0; i < RPL; ++i) {
+      const int r = q + kQ * i;
+      if (r < a.ell) a.B[r + (int64_t)pos * a.ldb] = x[i];
+    }
+    if (q == 0) {
+      if (a.src_top && pos < a.steps) a.src_top[pos] = c;
+      if (a.dst_low && c < a.steps) a.dst_low[c] = (pos >= a.steps) ? pos : -1;
+      if (a.perm) a.perm[pos] = c;
+    }
   }
 }
 
@@ -192,6 +246,8 @@ int sq_lm(int ell) {
 }
 
 int sq_record_stride(int lm) { return ((lm + 2 + 7) / 8) * 8; }
+
+int sq_columns_per_group() { return kSqCols; }
 
 template <int LM>
 static hipError_t launch_lm(const SqArgs& a, hipStream_t s) {
