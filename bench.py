@@ -139,6 +139,32 @@ def bench_rqrcp(args):
     ok = bool(np.array_equal(jpvt[:pre], first[:pre]))
     log(f"first-block pivots vs oracle: certified prefix {pre}, equal={ok}")
 
+    plain = None
+    if not args.no_plain:
+        # plain QRCP (Algorithm 2) on the same matrix, same device: the comparator
+        qsteps = max(1, min(args.steps, 2))
+        qcopies = [A0.clone(memory_format=torch.preserve_format) for _ in range(qsteps + 1)]
+        log(f"plain QRCP: 1 warmup + {qsteps} timed step(s)")
+        api.qrcp_factor(qcopies[0], nb=32, handle=h)
+        h.sync()
+        lib.rq_profile_start(h.ptr)
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for i in range(qsteps):
+            qj, _ = api.qrcp_factor(qcopies[1 + i], nb=32, handle=h)
+        torch.cuda.synchronize()
+        tq1 = time.perf_counter()
+        lib.rq_profile_stop(h.ptr)
+        h.sync()
+        qms = (tq1 - tq0) * 1e3 / qsteps
+        qprof = profile_table(h)
+        plain = {"ms_per_step": round(qms, 3), "value": round(flops / (qms * 1e-3) / 1e12, 4),
+                 "unit": "TFLOP/s", "nb": 32, "steps": qsteps,
+                 "rqrcp_speedup": round(qms / ms, 3),
+                 "kernels_ms_per_step": {k: round(v["ms"] / qsteps, 3) for k, v in qprof.items()}}
+        log(f"plain QRCP {qms:.2f} ms/step -> RQRCP speedup {qms / ms:.2f}x")
+        del qcopies
+
     roof = roofline(prof, args.steps)
     roof["share_of_step"] = round(prof[roof["kernel"]]["ms"] / args.steps / ms, 4)
     res = {
@@ -159,6 +185,7 @@ def bench_rqrcp(args):
         "roofline": roof,
         "first_block_pivots_match_oracle": ok,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
+        "plain_qrcp": plain,
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
@@ -176,6 +203,7 @@ def main():
     ap.add_argument("--n", type=int, default=8000)
     ap.add_argument("--cpu-k", type=int, default=512, help="pivots of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-QRCP comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "

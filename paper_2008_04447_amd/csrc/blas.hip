@@ -24,6 +24,7 @@ __global__ __launch_bounds__(256) void gemm_lx_kernel(GemmArgs g) {
   const int kb = blockIdx.y * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
   const bool nok = n < g.N;
+  const double* xc = g.X + (nok ? (g.xcol ? g.xcol[n] : (int64_t)n) : 0) * g.ldx;
   dx4 acc[PB];
 #pragma unroll
   for (int i = 0; i < PB; ++i) acc[i] = dx4{0.0, 0.0, 0.0, 0.0};
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(256) void gemm_lx_kernel(GemmArgs g) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = k0 + 4 * kq + s;
-      xb[s] = (nok && k < ke) ? g.X[k + (int64_t)n * g.ldx] : 0.0;
+      xb[s] = (nok && k < ke) ? xc[k] : 0.0;
 #pragma unroll
       for (int i = 0; i < PB; ++i) {
         const int p = 16 * i + (lane & 15);
@@ -124,8 +125,9 @@ __global__ __launch_bounds__(256) void reduce_plain_kernel(const double* part, i
 // Z = T^T W is an inner product of column i of T with that column.
 __global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64_t ldp,
                                                        int64_t sstride, int ks, int N,
-                                                       double* Z, const double* T, int64_t ldt,
-                                                       int bj) {
+                                                       double* Z, int64_t ldz, bool zero_pad,
+                                                       const double* T, int64_t ldt, int bj,
+                                                       bool trans) {
   __shared__ double s_T[64][65];
   __shared__ double s_w[4][64];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
@@ -143,8 +145,11 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64
   if (n >= N) return;
   double z = 0.0;
 #pragma unroll 16
-  for (int q = 0; q < 64; ++q) z += s_T[q][i] * s_w[cl][q];
-  Z[i + n * 64] = (i < bj) ? z : 0.0;
+  for (int q = 0; q < 64; ++q) z += (trans ? s_T[q][i] : s_T[i][q]) * s_w[cl][q];
+  if (i < bj)
+    Z[i + n * ldz] = z;
+  else if (zero_pad && i < ldz)
+    Z[i + n * ldz] = 0.0;
 }
 
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P, int N,
@@ -153,12 +158,21 @@ hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int k
   if (N <= 0) return hipSuccess;
   if (T) {
     hipLaunchKernelGGL(reduce_t_kernel, dim3((N + 3) / 4), dim3(256), 0, s, part, ldp, sstride,
-                       ks, N, out, T, ldt, bj);
+                       ks, N, out, (int64_t)64, true, T, ldt, bj, true);
   } else {
     const int64_t total = (int64_t)P * N;
     hipLaunchKernelGGL(reduce_plain_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                        s, part, ldp, sstride, ks, P, N, out, ldout);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_t(const double* part, int64_t ldp, int64_t sstride, int ks, int N,
+                           double* Z, int64_t ldz, bool zero_pad, const double* T, int64_t ldt,
+                           int bj, bool trans, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_t_kernel, dim3((N + 3) / 4), dim3(256), 0, s, part, ldp, sstride, ks,
+                     N, Z, ldz, zero_pad, T, ldt, bj, trans);
   return hipGetLastError();
 }
 
@@ -169,7 +183,8 @@ hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int k
 // consecutive rows of one column of C (coalesced loads and stores).
 __global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int M, int N,
                                                      const double* Y, int64_t ldy,
-                                                     const double* Z, int64_t ldz, int kpad) {
+                                                     const double* Z, int64_t ldz, int K,
+                                                     double alpha, double beta) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int rb = blockIdx.x * 64 + (wave & 1) * 32;
@@ -185,10 +200,10 @@ __global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int cc = cb + 16 * jb + kq + 4 * v;
-        acc[ib][jb][v] = (r < M && cc < N) ? C[r + (int64_t)cc * ldc] : 0.0;
+        acc[ib][jb][v] = (beta != 0.0 && r < M && cc < N) ? beta * C[r + (int64_t)cc * ldc] : 0.0;
       }
     }
-  for (int k0 = 0; k0 < kpad; k0 += 16) {
+  for (int k0 = 0; k0 < K; k0 += 16) {
     double za[2][4], yb[2][4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -196,12 +211,12 @@ __global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
         const int cc = cb + 16 * jb + l16;
-        za[jb][s] = (cc < N) ? -Z[k + (int64_t)cc * ldz] : 0.0;
+        za[jb][s] = (cc < N && k < K) ? alpha * Z[k + (int64_t)cc * ldz] : 0.0;
       }
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib) {
         const int r = rb + 16 * ib + l16;
-        yb[ib][s] = (r < M) ? Y[r + (int64_t)k * ldy] : 0.0;
+        yb[ib][s] = (r < M && k < K) ? Y[r + (int64_t)k * ldy] : 0.0;
       }
     }
 #pragma unroll
@@ -224,13 +239,19 @@ __global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int
     }
 }
 
+hipError_t launch_gemm_nn(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
+                          const double* Z, int64_t ldz, int K, double alpha, double beta,
+                          hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid((M + 63) / 64, (N + 63) / 64);
+  hipLaunchKernelGGL(update_kernel, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, Z, ldz, K, alpha,
+                     beta);
+  return hipGetLastError();
+}
+
 hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
                          const double* Z, int64_t ldz, int bj, hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  const int kpad = ((bj + 15) / 16) * 16;
-  dim3 grid((M + 63) / 64, (N + 63) / 64);
-  hipLaunchKernelGGL(update_kernel, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, Z, ldz, kpad);
-  return hipGetLastError();
+  return launch_gemm_nn(C, ldc, M, N, Y, ldy, Z, ldz, bj, -1.0, 1.0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -356,6 +377,118 @@ hipError_t launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ld
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy2d_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src,
                      lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <class TS>
+__global__ void gather_cols_kernel(const TS* src, int64_t lds, int r0, const int64_t* col,
+                                   double* dst, int64_t ldd, int rows, int cols) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= rows || c >= cols) return;
+  dst[r + (int64_t)c * ldd] = (double)src[(r0 + r) + col[c] * lds];
+}
+hipError_t launch_gather_cols(const void* src, bool src_f32, int64_t lds, int r0, const int64_t* col,
+                              double* dst, int64_t ldd, int rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 grid((rows + 255) / 256, cols);
+  if (src_f32)
+    hipLaunchKernelGGL(gather_cols_kernel<float>, grid, dim3(256), 0, s,
+                       static_cast<const float*>(src), lds, r0, col, dst, ldd, rows, cols);
+  else
+    hipLaunchKernelGGL(gather_cols_kernel<double>, grid, dim3(256), 0, s,
+                       static_cast<const double*>(src), lds, r0, col, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+__global__ void fill_kernel(double* X, int64_t ldx, int rows, int cols, double value,
+                            bool unit_diag) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int r = (int)(e % rows);
+  const int64_t c = e / rows;
+  X[r + c * ldx] = (unit_diag && r == c) ? 1.0 : value;
+}
+hipError_t launch_fill(double* X, int64_t ldx, int rows, int cols, double value, bool unit_diag,
+                       hipStream_t s) {
+  const int64_t total = (int64_t)rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, ldx,
+                     rows, cols, value, unit_diag);
+  return hipGetLastError();
+}
+
+__global__ void explicit_y_kernel(const double* A, int64_t lda, int M, int bj, double* Y,
+                                  int64_t ldy) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= M) return;
+  Y[r + (int64_t)c * ldy] = (c >= bj) ? 0.0 : (r < c ? 0.0 : (r == c ? 1.0 : A[r + (int64_t)c * lda]));
+}
+hipError_t launch_explicit_y(const double* A, int64_t lda, int M, int bj, double* Y, int64_t ldy,
+                             hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(explicit_y_kernel, dim3((M + 255) / 256, 64), dim3(256), 0, s, A, lda, M, bj,
+                     Y, ldy);
+  return hipGetLastError();
+}
+
+__global__ void copy_upper_kernel(const double* A, int64_t lda, int rows, int cols, double* R,
+                                  int64_t ldr) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= rows || c >= cols) return;
+  R[r + (int64_t)c * ldr] = (r <= c) ? A[r + (int64_t)c * lda] : 0.0;
+}
+hipError_t launch_copy_upper(const double* A, int64_t lda, int rows, int cols, double* R,
+                             int64_t ldr, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_upper_kernel, dim3((rows + 255) / 256, cols), dim3(256), 0, s, A, lda,
+                     rows, cols, R, ldr);
+  return hipGetLastError();
+}
+
+// X1(i, c) = sum_{q <= c} G(q, i) T2(q, c)   (i < c0, c < bj)
+__global__ void tcomp1_kernel(const double* G, const double* T2, int64_t ldt2, int c0, int bj,
+                              double* X1) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= c0 || c >= bj) return;
+  double acc = 0.0;
+  for (int q = 0; q <= c; ++q) acc += G[q + (int64_t)i * 64] * T2[q + (int64_t)c * ldt2];
+  X1[i + (int64_t)c * c0] = acc;
+}
+// T(i, c0 + c) = -sum_{s = i}^{c0-1} T(i, s) X1(s, c)
+__global__ void tcomp2_kernel(double* T, int64_t ldt, int c0, int bj, const double* X1) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= c0 || c >= bj) return;
+  double acc = 0.0;
+  for (int s2 = i; s2 < c0; ++s2) acc += T[i + (int64_t)s2 * ldt] * X1[s2 + (int64_t)c * c0];
+  T[i + (int64_t)(c0 + c) * ldt] = -acc;
+}
+hipError_t launch_tcompose(double* T, int64_t ldt, int c0, int bj, const double* G,
+                           const double* T2, int64_t ldt2, double* X1, hipStream_t s) {
+  if (c0 <= 0 || bj <= 0) return hipSuccess;
+  dim3 grid((c0 + 255) / 256, bj);
+  hipLaunchKernelGGL(tcomp1_kernel, grid, dim3(256), 0, s, G, T2, ldt2, c0, bj, X1);
+  hipLaunchKernelGGL(tcomp2_kernel, grid, dim3(256), 0, s, T, ldt, c0, bj, X1);
+  return hipGetLastError();
+}
+
+__global__ void scatter_t_kernel(const double* R, int64_t ldr, int k, int n, const int64_t* col,
+                                 double* Z0T, int64_t ldz) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= k || c >= n) return;
+  Z0T[col[c] + (int64_t)i * ldz] = R[i + (int64_t)c * ldr];
+}
+hipError_t launch_scatter_t(const double* R, int64_t ldr, int k, int n, const int64_t* col,
+                            double* Z0T, int64_t ldz, hipStream_t s) {
+  if (k <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_t_kernel, dim3((k + 255) / 256, n), dim3(256), 0, s, R, ldr, k, n, col,
+                     Z0T, ldz);
   return hipGetLastError();
 }
 

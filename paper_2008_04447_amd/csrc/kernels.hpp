@@ -51,6 +51,7 @@ struct GemmArgs {
   double* out; int64_t ldout; int64_t split_stride;
   double alpha, beta;                  // ksplit == 1: out = alpha * LX + beta * C
   const double* C; int64_t ldc;
+  const int64_t* xcol = nullptr;       // optional: column n of X is X + xcol[n] * ldx
 };
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
 void plan_split(int K, int N, int* ksplit, int* kchunk);
@@ -60,10 +61,39 @@ void plan_split(int K, int N, int* ksplit, int* kchunk);
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P,
                          int N, double* out, int64_t ldout, const double* T, int64_t ldt,
                          int bj, hipStream_t s);
+// Z(0:bj, n) = T^T W(:, n) (trans) or T W(:, n) with W the split-K sum; Z leading
+// dimension ldz (rows bj..min(ldz,64)-1 are zeroed only when zero_pad is set).
+hipError_t launch_reduce_t(const double* part, int64_t ldp, int64_t sstride, int ks, int N,
+                           double* Z, int64_t ldz, bool zero_pad, const double* T, int64_t ldt,
+                           int bj, bool trans, hipStream_t s);
 
-// C(M x N) -= Y(M x K) Z(K x N), K = 16 * ceil(bj / 16) <= 64, Z leading dim ldz.
+// C(M x N) -= Y(M x K) Z(K x N) with K = bj (Y, Z read only for k < K).
 hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
                          const double* Z, int64_t ldz, int bj, hipStream_t s);
+// C(M x N) = beta C + alpha Y(M x K) Z(K x N), any K (FP64 MFMA, 64 x 64 tiles).
+hipError_t launch_gemm_nn(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
+                          const double* Z, int64_t ldz, int K, double alpha, double beta,
+                          hipStream_t s);
+// dst(r, c) = src(r0 + r, col[c]) for r < rows, c < cols (src double or float).
+hipError_t launch_gather_cols(const void* src, bool src_f32, int64_t lds, int r0, const int64_t* col,
+                              double* dst, int64_t ldd, int rows, int cols, hipStream_t s);
+// X(r, c) = value for r < rows, c < cols; with diag set, X(c, c) = 1 additionally.
+hipError_t launch_fill(double* X, int64_t ldx, int rows, int cols, double value, bool unit_diag,
+                       hipStream_t s);
+// Explicit unit-lower reflectors of an in-place QR block: Y(r, c) = 0 (r < c),
+// 1 (r == c), A(r, c) (r > c), for c < bj; columns bj..63 zero.
+hipError_t launch_explicit_y(const double* A, int64_t lda, int M, int bj, double* Y, int64_t ldy,
+                             hipStream_t s);
+// Upper triangle of an in-place block: R(r, c) = A(r, c) for r <= c < cols, 0 below.
+hipError_t launch_copy_upper(const double* A, int64_t lda, int rows, int cols, double* R,
+                             int64_t ldr, hipStream_t s);
+// T12 = -T11 (G^T T2): G is bj x c0 (ld 64), T2 bj x bj, T11 c0 x c0; result into
+// T(0:c0, c0:c0+bj).  X1 is c0 x 64 scratch.
+hipError_t launch_tcompose(double* T, int64_t ldt, int c0, int bj, const double* G,
+                           const double* T2, int64_t ldt2, double* X1, hipStream_t s);
+// Z0T(col[c], i) = R(i, c) for i < k, c < n  (Z0^T = (R P^T)^T).
+hipError_t launch_scatter_t(const double* R, int64_t ldr, int k, int n, const int64_t* col,
+                            double* Z0T, int64_t ldz, hipStream_t s);
 
 // Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr.
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr,

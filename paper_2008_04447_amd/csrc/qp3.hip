@@ -1,0 +1,391 @@
+// Plain column-pivoted QR on the GPU: Algorithm 2 (QRCP with BLAS-3
+// reflection blocking, Section 2.1), the baseline RQRCP is compared with.
+//
+// Per column j of a block starting at column i (jb = j - i reflectors so far):
+//   pivot kernel (one workgroup): argmax of the trailing norms (ties: lowest
+//     position), swap columns j <-> p (all rows), norms, jpvt and the stored
+//     inner products W^T; bring column j up to date with the block's earlier
+//     reflectors, form its reflector, and u = Y(j:, 0:jb)^T v;
+//   gemv kernel (all columns): the adjusted inner products
+//     w_c = tau (v^T A(j:, c) - u^T W^T(0:jb, c)) over the whole trailing matrix,
+//     the update of row j, and the norm downdate nu_c^2 -= A(j, c)^2 with an
+//     exact recomputation when cancellation makes the downdate unreliable.
+// At the end of a block the trailing matrix receives A -= Y W^T (the MFMA
+// update kernel) and its column norms are recomputed exactly.
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.hpp"
+#include "host.hpp"
+
+namespace rq {
+
+constexpr int kQpThreads = 1024;
+constexpr int kQpRows = 256;                // rows of column j handled by one workgroup
+
+struct Qp3Args {
+  double* A;
+  int64_t lda;
+  int m, n, i, j;     // block start i, current column j
+  int nwg;            // workgroups of the pivot kernel
+  double* vn1;        // current trailing norms
+  double* vn2;        // norms at their last exact computation
+  int64_t* jpvt;
+  double* Wt;         // inner products, Wt[q + c * 64]
+  double* part;       // per-workgroup partials: [2][nwg][72] (norm, alpha, u_q)
+  uint32_t* counter;
+  uint32_t* abort_flag;
+  double* tau;
+  int64_t* status;
+};
+
+constexpr int kQpRec = 72;                  // doubles per workgroup record
+
+// Pivot step of column j, spread over nwg workgroups that each own 256 rows
+// of column j (rows j + 256 w ...).  Every workgroup finds the same pivot from
+// the norms, swaps its share of the two columns, brings its rows of column j up
+// to date with the block's reflectors and publishes its partial norm; after one
+// exchange each workgroup forms the same reflector, scales its rows and
+// publishes its partial u = Y^T v, which the gemv kernel sums.
+__global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int i = a.i, j = a.j, jb = j - i;
+  const int wg = blockIdx.x;
+  if (prior_timeout(a.status)) return;
+  __shared__ double s_wv[16];
+  __shared__ int s_wp[16];
+  __shared__ double s_w[64];
+  __shared__ double s_x[kQpRows];
+  __shared__ double s_red[16][64];
+  __shared__ int s_piv;
+  __shared__ double s_sc[3];
+  // 1. argmax of the trailing norms (identical in every workgroup)
+  double bv = -1.0;
+  int bp = INT_MAX;
+  for (int c = j + t; c < a.n; c += kQpThreads) {
+    const double v = a.vn1[c];
+    if (better(v, c, bv, bp)) {
+      bv = v;
+      bp = c;
+    }
+  }
+  int who = 0;
+  wave_argmax(bv, bp, who);
+  if (lane == 0) {
+    s_wv[wave] = bv;
+    s_wp[wave] = bp;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double v = s_wv[0];
+    int p = s_wp[0];
+    for (int w = 1; w < 16; ++w)
+      if (better(s_wv[w], s_wp[w], v, p)) {
+        v = s_wv[w];
+        p = s_wp[w];
+      }
+    if (p == INT_MAX || !(v <= 1.7976931348623157e308)) {
+      if (wg == 0) raise_status(a.status, kErrNonFinite);
+      p = j;
+    }
+    s_piv = p;
+  }
+  __syncthreads();
+  const int p = s_piv;
+  if (t < 64) s_w[t] = (t < jb) ? a.Wt[t + (int64_t)p * 64] : 0.0;   // W^T of the new column j
+  // 2. swap columns j and p: rows 0..j-1 strided over workgroups, rows j.. by owner
+  if (p != j) {
+    for (int r = wg * kQpThreads + t; r < j; r += a.nwg * kQpThreads) {
+      const double x = a.A[r + (int64_t)j * a.lda];
+      a.A[r + (int64_t)j * a.lda] = a.A[r + (int64_t)p * a.lda];
+      a.A[r + (int64_t)p * a.lda] = x;
+    }
+  }
+  __syncthreads();   // s_w is read by every wave below
+  // 3. own rows of column j (after the swap), brought up to date
+  const int r = j + wg * kQpRows + t;
+  const bool mine = t < kQpRows && r < a.m;
+  double x = 0.0;
+  if (mine) {
+    x = a.A[r + (int64_t)p * a.lda];
+    if (p != j) a.A[r + (int64_t)p * a.lda] = a.A[r + (int64_t)j * a.lda];
+    for (int q = 0; q < jb; ++q) x -= a.A[r + (int64_t)(i + q) * a.lda] * s_w[q];
+  }
+  double ss = (mine && r > j) ? x * x : 0.0;
+  ss = wave_sum(ss);
+  if (lane == 0) s_red[wave][0] = ss;
+  __syncthreads();
+  double* rec = a.part + (int64_t)wg * kQpRec;
+  if (t == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += s_red[w][0];
+    rec[0] = s;
+    rec[1] = (wg == 0) ? x : 0.0;          // row j lives in workgroup 0, thread 0
+  }
+  if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, 0u, a.status)) return;
+  // Every workgroup has finished reading the norms and W^T(:, p), so workgroup 0
+  // may now swap the per-column metadata.
+  if (wg == 0 && p != j) {
+    if (t < jb) {
+      const double w0 = a.Wt[t + (int64_t)j * 64];
+      a.Wt[t + (int64_t)j * 64] = a.Wt[t + (int64_t)p * 64];
+      a.Wt[t + (int64_t)p * 64] = w0;
+    }
+    if (t == 0) {
+      double y = a.vn1[j];
+      a.vn1[j] = a.vn1[p];
+      a.vn1[p] = y;
+      y = a.vn2[j];
+      a.vn2[j] = a.vn2[p];
+      a.vn2[p] = y;
+      const int64_t q = a.jpvt[j];
+      a.jpvt[j] = a.jpvt[p];
+      a.jpvt[p] = q;
+    }
+  }
+  // 4. reflector, identical in every workgroup (fixed-order sum of partials)
+  if (t == 0) {
+    double tail = 0.0;
+    for (int w = 0; w < a.nwg; ++w) tail += a.part[(int64_t)w * kQpRec];
+    const double alpha = a.part[1];
+    const double s2 = tail + alpha * alpha;
+    double beta = 0.0, tau = 0.0, scale = 0.0;
+    if (s2 > 0.0) {
+      const double sn = sqrt(s2);
+      beta = (alpha >= 0.0) ? -sn : sn;
+      scale = 1.0 / (alpha - beta);
+      tau = (beta - alpha) / beta;
+    }
+    s_sc[0] = beta;
+    s_sc[1] = tau;
+    s_sc[2] = scale;
+  }
+  __syncthreads();
+  const double beta = s_sc[0], tau = s_sc[1], scale = s_sc[2];
+  double v = 0.0;
+  if (mine) {
+    v = (r == j) ? 1.0 : x * scale;
+    a.A[r + (int64_t)j * a.lda] = (r == j) ? beta : v;
+  }
+  if (t < kQpRows) s_x[t] = v;
+  if (wg == 0 && t == 0) a.tau[j] = tau;
+  __syncthreads();
+  // 5. partial u_q = sum over own rows of Y(r, q) v(r), q < jb
+  {
+    const int g = t & 15, q = t >> 4;        // 16 row groups x 64 reflectors
+    double acc = 0.0;
+    if (q < jb) {
+      for (int rr = g; rr < kQpRows; rr += 16) {
+        const int row = j + wg * kQpRows + rr;
+        if (row < a.m) acc += a.A[row + (int64_t)(i + q) * a.lda] * s_x[rr];
+      }
+    }
+    s_red[g][q] = acc;
+  }
+  __syncthreads();
+  double* rec2 = a.part + ((int64_t)a.nwg + wg) * kQpRec;
+  if (t < 64) {
+    double s = 0.0;
+    for (int g = 0; g < 16; ++g) s += s_red[g][t];
+    rec2[t] = (t < jb) ? s : 0.0;
+  }
+}
+
+// One wave per trailing column (4 columns per wave, 16 per workgroup).
+__global__ __launch_bounds__(256) void qp3_gemv_kernel(Qp3Args a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = a.i, j = a.j, jb = j - i;
+  const double tau = a.tau[j];
+  const double* v = a.A + (int64_t)j * a.lda;   // v(j) = 1 implied, tails below
+  const double tol = 1.4901161193847656e-08;    // sqrt(eps): downdate reliability bound
+  __shared__ double s_u[64];
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    if ((int)threadIdx.x < jb)
+      for (int w = 0; w < a.nwg; ++w) s += a.part[((int64_t)a.nwg + w) * kQpRec + threadIdx.x];
+    s_u[threadIdx.x] = s;
+  }
+  __syncthreads();
+  // the four columns of this wave stream together so v is read once for them
+  const int c0 = j + 1 + blockIdx.x * 16 + wave * 4;
+  double dots[4];
+  {
+    const double* cols[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) cols[s] = a.A + (int64_t)min(c0 + s, a.n - 1) * a.lda;
+    double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    int r = j + 1 + lane;
+    for (; r + 64 < a.m; r += 128) {
+      const double v0 = v[r], v1 = v[r + 64];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        acc[s][0] += v0 * cols[s][r];
+        acc[s][1] += v1 * cols[s][r + 64];
+      }
+    }
+    if (r < a.m) {
+      const double v0 = v[r];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s][0] += v0 * cols[s][r];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dots[s] = wave_sum(acc[s][0] + acc[s][1]);
+  }
+  for (int s = 0; s < 4; ++s) {
+    const int c = c0 + s;
+    if (c >= a.n) break;
+    const double* col = a.A + (int64_t)c * a.lda;
+    const double dot = dots[s] + col[j];
+    double corr = 0.0, yw = 0.0;
+    if (lane < jb) {
+      const double wq = a.Wt[lane + (int64_t)c * 64];
+      corr = s_u[lane] * wq;
+      yw = a.A[j + (int64_t)(i + lane) * a.lda] * wq;   // Y(j, q) W^T(q, c)
+    }
+    corr = wave_sum(corr);
+    yw = wave_sum(yw);
+    const double w = tau * (dot - corr);
+    const double rowv = col[j] - yw - w;
+    if (lane == 0) {
+      a.Wt[jb + (int64_t)c * 64] = w;
+      a.A[j + (int64_t)c * a.lda] = rowv;
+    }
+    // norm downdate with the reliability test of LAPACK's blocked QRCP
+    double nv = a.vn1[c];
+    bool redo = false;
+    if (nv != 0.0) {
+      double tt = fabs(rowv) / nv;
+      tt = fmax(0.0, (1.0 + tt) * (1.0 - tt));
+      const double ratio = nv / a.vn2[c];
+      if (tt * ratio * ratio <= tol)
+        redo = true;
+      else
+        nv *= sqrt(tt);
+    }
+    if (redo) {
+      // exact norm of rows j+1.. of column c brought up to date with the block
+      double acc = 0.0;
+      for (int rr = j + 1 + lane; rr < a.m; rr += 64) {
+        double x = col[rr];
+        for (int q = 0; q < jb; ++q) x -= a.A[rr + (int64_t)(i + q) * a.lda] * a.Wt[q + (int64_t)c * 64];
+        x -= v[rr] * w;
+        acc += x * x;
+      }
+      nv = sqrt(wave_sum(acc));
+      if (lane == 0) a.vn2[c] = nv;
+    }
+    if (lane == 0) a.vn1[c] = nv;
+  }
+}
+
+// Exact column norms of rows r0..m-1 for columns c0..n-1 (one wave per column).
+__global__ __launch_bounds__(256) void qp3_norms_kernel(const double* A, int64_t lda, int m, int r0,
+                                                        int c0, int n, double* vn1, double* vn2) {
+  const int lane = threadIdx.x & 63;
+  const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const double* col = A + (int64_t)c * lda;
+  double s0 = 0.0, s1 = 0.0;
+  int r = r0 + lane;
+  for (; r + 64 < m; r += 128) {
+    s0 += col[r] * col[r];
+    s1 += col[r + 64] * col[r + 64];
+  }
+  for (; r < m; r += 64) s0 += col[r] * col[r];
+  const double nv = sqrt(wave_sum(s0 + s1));
+  if (lane == 0) {
+    vn1[c] = nv;
+    vn2[c] = nv;
+  }
+}
+
+}  // namespace rq
+
+using namespace rq;
+
+extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t nb,
+                                 double* A, int64_t lda, int64_t* jpvt, double* tau) {
+  if (!h) return -1;
+  if (m < 0) return -2;
+  if (n < 0 || n > RQ_MAX_N) return -3;
+  if (k < 0 || k > std::min(m, n)) return -4;
+  if (nb < 1 || nb > 64) return -5;
+  if (!valid_ptr(A, m * n)) return -6;
+  if (lda < std::max<int64_t>(1, m)) return -7;
+  if (!valid_ptr(jpvt, n)) return -8;
+  if (!valid_ptr(tau, k)) return -9;
+  if (n == 0) return RQ_OK;
+  DeviceGuard guard(h->device);
+  hipStream_t s = h->stream;
+  RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
+  if (k == 0) return RQ_OK;
+  const int max_nwg = (int)((m + kQpRows - 1) / kQpRows);
+  const size_t n_part = (size_t)2 * max_nwg * kQpRec;
+  const size_t need = 2 * padded_bytes(n) + padded_bytes((size_t)64 * n) + padded_bytes(n_part);
+  RQ_TRY(reserve(h, need));
+  Carve cv(h->ws);
+  double* vn1 = cv.take<double>(n);
+  double* vn2 = cv.take<double>(n);
+  double* Wt = cv.take<double>((size_t)64 * n);
+  double* part = cv.take<double>(n_part);
+  {
+    KTimer kt(h, K_QP3_ROW, 2.0 * m * n, 8.0 * m * n);
+    hipLaunchKernelGGL(qp3_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, A, lda,
+                       (int)m, 0, 0, (int)n, vn1, vn2);
+    RQ_CHECK(h, hipGetLastError());
+  }
+  Qp3Args a{};
+  a.A = A;
+  a.lda = lda;
+  a.m = (int)m;
+  a.n = (int)n;
+  a.vn1 = vn1;
+  a.vn2 = vn2;
+  a.jpvt = jpvt;
+  a.Wt = Wt;
+  a.part = part;
+  a.counter = h->sync;
+  a.abort_flag = h->sync + 1;
+  a.tau = tau;
+  a.status = h->status;
+  for (int64_t i = 0; i < k; i += nb) {
+    const int64_t iend = std::min(k, i + nb);
+    a.i = (int)i;
+    for (int64_t j = i; j < iend; ++j) {
+      a.j = (int)j;
+      const double jb = (double)(j - i);
+      {
+        KTimer kt(h, K_QP3_PIVOT, 4.0 * (m - j) * (jb + 1),
+                  8.0 * ((double)(m - j) * (jb + 2) + 2.0 * m));
+        a.nwg = (int)((m - j + kQpRows - 1) / kQpRows);
+        RQ_CHECK(h, launch_zero_u32(h->sync, 2, s));
+        hipLaunchKernelGGL(qp3_pivot_kernel, dim3(a.nwg), dim3(kQpThreads), 0, s, a);
+        RQ_CHECK(h, hipGetLastError());
+      }
+      const int64_t nt = n - j - 1;
+      if (nt > 0) {
+        KTimer kt(h, K_QP3_GEMV, 2.0 * (m - j) * (double)nt,
+                  8.0 * ((double)(m - j) * nt + (double)(m - j)));
+        hipLaunchKernelGGL(qp3_gemv_kernel, dim3((unsigned)((nt + 15) / 16)), dim3(256), 0, s, a);
+        RQ_CHECK(h, hipGetLastError());
+      }
+    }
+    // block reflection of the trailing matrix, then exact norms again
+    const int64_t j1 = iend;                      // first column after the block
+    const int kb = (int)(iend - i);
+    if (j1 < n && j1 < m) {
+      {
+        KTimer kt(h, K_UPDATE, 2.0 * kb * (double)(m - j1) * (n - j1),
+                  8.0 * (2.0 * (m - j1) * (double)(n - j1)));
+        RQ_CHECK(h, launch_update(A + j1 + j1 * lda, lda, (int)(m - j1), (int)(n - j1),
+                                  A + j1 + i * lda, lda, Wt + j1 * 64, 64, kb, s));
+      }
+      KTimer kt(h, K_QP3_ROW, 2.0 * (double)(m - j1) * (n - j1), 8.0 * (double)(m - j1) * (n - j1));
+      hipLaunchKernelGGL(qp3_norms_kernel, dim3((unsigned)((n - j1 + 3) / 4)), dim3(256), 0, s, A,
+                         lda, (int)m, (int)j1, (int)j1, (int)n, vn1, vn2);
+      RQ_CHECK(h, hipGetLastError());
+    }
+  }
+  return RQ_OK;
+}
