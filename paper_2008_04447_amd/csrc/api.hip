@@ -100,6 +100,62 @@ rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* 
   return RQ_OK;
 }
 
+static void plan_split32(int K, int N, int* ks, int* kc) {
+  plan_split(K, N, ks, kc);
+  *kc = ((*kc + 31) / 32) * 32;
+  *ks = (K + *kc - 1) / *kc;
+  if (*ks < 1) *ks = 1;
+}
+
+size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n) {
+  int ks, kc;
+  plan_split32((int)m, (int)n, &ks, &kc);
+  return (size_t)ks * ell * n;
+}
+
+rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, double* out,
+                               int64_t ldout) {
+  int ks, kc;
+  plan_split32(g.K, g.N, &ks, &kc);
+  g.ksplit = ks;
+  g.kchunk = kc;
+  const double fl = 2.0 * g.P * (double)g.K * g.N;
+  const double by = 4.0 * (double)g.K * g.N + 8.0 * ((double)g.P * g.K + (double)ks * g.P * g.N);
+  if (ks == 1) {
+    g.out = out;
+    g.ldout = ldout;
+    g.split_stride = 0;
+    KTimer kt(h, cls, fl, by);
+    RQ_CHECK(h, launch_gemm_lx_bf16(g, h->stream));
+    return RQ_OK;
+  }
+  g.out = part;
+  g.ldout = g.P;
+  g.split_stride = (int64_t)g.P * g.N;
+  {
+    KTimer kt(h, cls, fl, by);
+    RQ_CHECK(h, launch_gemm_lx_bf16(g, h->stream));
+  }
+  KTimer kt(h, K_REDUCE, (double)(ks - 1) * g.P * g.N, 8.0 * (ks + 1.0) * g.P * g.N);
+  RQ_CHECK(h, launch_reduce(part, g.P, g.split_stride, ks, g.P, g.N, out, ldout, nullptr, 0, 0,
+                            h->stream));
+  return RQ_OK;
+}
+
+rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
+                      const float* A, int64_t lda, double* B, int64_t ldb, double* part) {
+  GemmArgsF g{};
+  g.L = Omega;
+  g.sLp = 1;
+  g.sLk = ldo;
+  g.X = A;
+  g.ldx = lda;
+  g.P = ell;
+  g.K = (int)m;
+  g.N = (int)n;
+  return gemm_lx_bf16_reduced(h, K_SKETCH, g, part, B, ldb);
+}
+
 size_t sq_rec_doubles(int ell, int64_t N) {
   const int lm = sq_lm(ell);
   return (size_t)2 * ((N + 255) / 256) * sq_record_stride(lm);
@@ -303,13 +359,16 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
   if (lda < std::max<int64_t>(1, m)) return -9;
   if (!valid_ptr(B, ell * n)) return -10;
   if (ldb < ell) return -11;
-  if (prec != RQ_FP64) return RQ_E_UNSUPPORTED;
   if (n == 0) return RQ_OK;
   DeviceGuard guard(h->device);
-  const size_t np = sketch_part_doubles((int)ell, m, n);
+  const size_t np = std::max(sketch_part_doubles((int)ell, m, n),
+                             sketch_part_doubles_bf16((int)ell, m, n));
   RQ_TRY(reserve(h, padded_bytes(np)));
   Carve cv(h->ws);
   double* part = cv.take<double>(np);
+  if (prec == RQ_MIXED_BF16)
+    return sketch_bf16(h, (int)ell, m, n, Omega, ldo, static_cast<const float*>(A), lda, B, ldb,
+                       part);
   return sketch_fp64(h, (int)ell, m, n, Omega, ldo, static_cast<const double*>(A), lda, B, ldb,
                      part);
 }

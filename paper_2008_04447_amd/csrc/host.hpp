@@ -137,6 +137,13 @@ size_t panel_rec_doubles(int64_t M);
 size_t sketch_part_doubles(int ell, int64_t m, int64_t n);
 rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
                       const double* A, int64_t lda, double* B, int64_t ldb, double* part);
+// B = Omega A with A FP32 on BF16 MFMA (split-K partials summed in FP64).
+rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
+                      const float* A, int64_t lda, double* B, int64_t ldb, double* part);
+// Y^T-style product with FP32 X on BF16 MFMA, reduced into out (leading dim ldout).
+rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, double* out,
+                               int64_t ldout);
+size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm);
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,

@@ -56,6 +56,20 @@ struct GemmArgs {
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
 void plan_split(int K, int N, int* ksplit, int* kchunk);
 
+// ---- BF16 MFMA contractions (FP32 accumulate, FP64 results) -----------------
+struct GemmArgsF {
+  const double* L; int64_t sLp, sLk;   // L(p, k), rounded to BF16
+  const float* X; int64_t ldx;         // X(k, n) = X[k + n * ldx], rounded to BF16
+  int P, K, N;
+  int ksplit, kchunk;                  // kchunk a multiple of 32
+  double* out; int64_t ldout; int64_t split_stride;   // partial s at out + s * split_stride
+  const int64_t* xcol = nullptr;       // optional column map of X
+};
+hipError_t launch_gemm_lx_bf16(const GemmArgsF& g, hipStream_t s);
+// C(M x N) = Y(M x K) Z(K x N) with Y FP32 and Z FP64, both rounded to BF16.
+hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float* Y, int64_t ldy,
+                               const double* Z, int64_t ldz, int K, hipStream_t s);
+
 // sum of split-K partials; with T != null the result is Z = T^T W written with
 // leading dimension ldz = 64 (rows bj..63 zero) -- the trailing-update operand.
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P,

@@ -33,7 +33,9 @@ struct TrWork {
 };
 
 static size_t split_part_bound(int64_t n, int64_t k) {
-  return (size_t)64 * (65536 + (size_t)n + (size_t)k);
+  // split-K partials: ks * 64 * N <= 64 (65536 + N) for every product here, and
+  // the sketch's ks * ell * n fits the same bound (ell <= 96 < 2 * 64, ks <= 32)
+  return (size_t)64 * (65536 + (size_t)n + (size_t)k) + (size_t)32 * 96 * (size_t)n;
 }
 
 static size_t trwork_doubles(int64_t m, int64_t n, int64_t k, int ell) {
@@ -97,7 +99,7 @@ static rq_status gemm_lx_reduced(rq_handle h, int cls, GemmArgs g, double* part,
 
 // The TRQRCP block loop (FP64).  A is m x n double, never written.
 static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int ell,
-                             const double* A, int64_t lda, const double* Omega, int64_t ldo,
+                             const void* Av, bool f32, int64_t lda, const double* Omega, int64_t ldo,
                              int64_t* jpvt, double* Y, int64_t ldy, double* T, int64_t ldt,
                              double* R, int64_t ldr, TrWork& w) {
   hipStream_t s = h->stream;
@@ -108,7 +110,12 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
     RQ_CHECK(h, launch_fill(R, ldr, (int)k, (int)n, 0.0, false, s));
     RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
   }
-  RQ_TRY(sketch_fp64(h, ell, m, n, Omega, ldo, A, lda, w.sample, ell, w.part));
+  const double* A = static_cast<const double*>(Av);
+  const float* Af = static_cast<const float*>(Av);
+  if (f32)
+    RQ_TRY(sketch_bf16(h, ell, m, n, Omega, ldo, Af, lda, w.sample, ell, w.part));
+  else
+    RQ_TRY(sketch_fp64(h, ell, m, n, Omega, ldo, A, lda, w.sample, ell, w.part));
   for (int64_t col0 = 0; col0 < k; col0 += b) {
     const int bj = (int)std::min<int64_t>(b, k - col0);
     const int64_t N = n - col0, M = m - col0, Nt = N - bj;
@@ -126,7 +133,8 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
     // 3. selected columns of A - Y W^T, rows col0..m-1
     {
       KTimer kt(h, K_TR_SELECT, 2.0 * (double)M * bj * col0, 8.0 * (double)M * bj * 2.0);
-      RQ_CHECK(h, launch_gather_cols(A, false, lda, (int)col0, jpvt + col0, w.awork, m, (int)M, bj, s));
+      RQ_CHECK(h, launch_gather_cols(Av, f32, lda, (int)col0, jpvt + col0, w.awork, m, (int)M, bj,
+                                     s));
       if (col0 > 0)
         RQ_CHECK(h, launch_gemm_nn(w.awork, m, (int)M, bj, Y + col0, ldy, w.wt + col0 * k, k,
                                    (int)col0, -1.0, 1.0, s));
@@ -158,17 +166,31 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
     }
     if (Nt > 0) {
       // 5b. S = Y2^T A P over the trailing positions (the one pass over A per block)
-      GemmArgs g{};
-      g.L = w.ybuf;
-      g.sLp = m;
-      g.sLk = 1;
-      g.X = A + col0;
-      g.ldx = lda;
-      g.xcol = jpvt + col0 + bj;
-      g.P = bj;
-      g.K = (int)M;
-      g.N = (int)Nt;
-      RQ_TRY(gemm_lx_reduced(h, K_INNER, g, w.part, w.sbuf, 64));
+      if (f32) {
+        GemmArgsF g{};
+        g.L = w.ybuf;
+        g.sLp = m;
+        g.sLk = 1;
+        g.X = Af + col0;
+        g.ldx = lda;
+        g.xcol = jpvt + col0 + bj;
+        g.P = bj;
+        g.K = (int)M;
+        g.N = (int)Nt;
+        RQ_TRY(gemm_lx_bf16_reduced(h, K_INNER, g, w.part, w.sbuf, 64));
+      } else {
+        GemmArgs g{};
+        g.L = w.ybuf;
+        g.sLp = m;
+        g.sLk = 1;
+        g.X = A + col0;
+        g.ldx = lda;
+        g.xcol = jpvt + col0 + bj;
+        g.P = bj;
+        g.K = (int)M;
+        g.N = (int)Nt;
+        RQ_TRY(gemm_lx_reduced(h, K_INNER, g, w.part, w.sbuf, 64));
+      }
       // 5c. S -= G W^T(0:col0, trailing)
       if (col0 > 0) {
         GemmArgs u{};
@@ -201,7 +223,7 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
       {
         KTimer kt(h, K_TR_ROWS, 2.0 * bj * (double)(col0 + bj) * Nt,
                   8.0 * ((double)(col0 + bj) * Nt + 3.0 * bj * Nt));
-        RQ_CHECK(h, launch_gather_cols(A, false, lda, (int)col0, jpvt + col0 + bj,
+        RQ_CHECK(h, launch_gather_cols(Av, f32, lda, (int)col0, jpvt + col0 + bj,
                                        R + col0 + (col0 + bj) * ldr, ldr, bj, (int)Nt, s));
         GemmArgs u{};
         u.L = Y + col0;
@@ -335,7 +357,6 @@ extern "C" rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64
   if (ldt < std::max<int64_t>(1, k)) return -16;
   if (!valid_ptr(R, k * n)) return -17;
   if (ldr < std::max<int64_t>(1, k)) return -18;
-  if (prec != RQ_FP64) return RQ_E_UNSUPPORTED;
   if (n == 0) return RQ_OK;
   DeviceGuard guard(h->device);
   if (k == 0) {
@@ -343,11 +364,11 @@ extern "C" rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64
     return RQ_OK;
   }
   const int ell = (int)(b + p);
-  RQ_TRY(reserve(h, trwork_doubles(m, n, k, ell) + padded_bytes(sketch_part_doubles(ell, m, n))));
+  RQ_TRY(reserve(h, trwork_doubles(m, n, k, ell)));
   Carve cv(h->ws);
   TrWork w = carve_trwork(cv, m, n, k, ell);
-  return trqrcp_core(h, m, n, k, b, ell, static_cast<const double*>(A), lda, Omega, ldo, jpvt, Y,
-                     ldy, T, ldt, R, ldr, w);
+  return trqrcp_core(h, m, n, k, b, ell, A, prec == RQ_MIXED_BF16, lda, Omega, ldo, jpvt, Y, ldy,
+                     T, ldt, R, ldr, w);
 }
 
 extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
@@ -362,7 +383,6 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   if (!valid_ptr(V, n * k)) return -16;
   if (ldv < std::max<int64_t>(1, n)) return -17;
   if (!valid_ptr(jpvt, n)) return -18;
-  if (prec != RQ_FP64) return RQ_E_UNSUPPORTED;
   if (n == 0 || k == 0) {
     if (n > 0) RQ_CHECK(h, launch_iota(jpvt, (int)n, h->stream));
     return RQ_OK;
@@ -374,8 +394,7 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
                        padded_bytes((size_t)k * n) + padded_bytes((size_t)n * k) +
                        padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
                        padded_bytes((size_t)k + 64);
-  RQ_TRY(reserve(h, trwork_doubles(m, n, k, ell) + padded_bytes(sketch_part_doubles(ell, m, n)) +
-                        extra));
+  RQ_TRY(reserve(h, trwork_doubles(m, n, k, ell) + extra));
   Carve cv(h->ws);
   TrWork w = carve_trwork(cv, m, n, k, ell);
   double* Yw = cv.take<double>((size_t)m * k);
@@ -386,10 +405,10 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   double* Tb = cv.take<double>((size_t)64 * k);
   double* Tb2 = cv.take<double>((size_t)64 * k);
   double* tauq = cv.take<double>((size_t)k + 64);
-  const double* Ad = static_cast<const double*>(A);
+  const bool f32 = prec == RQ_MIXED_BF16;
   hipStream_t s = h->stream;
   // 1. TRQRCP: A P ~ Q R
-  RQ_TRY(trqrcp_core(h, m, n, k, b, ell, Ad, lda, Omega, ldo, jpvt, Yw, m, Tw, k, Rw, k, w));
+  RQ_TRY(trqrcp_core(h, m, n, k, b, ell, A, f32, lda, Omega, ldo, jpvt, Yw, m, Tw, k, Rw, k, w));
   // 2. Z0 = R P^T, stored transposed (n x k)
   {
     KTimer kt(h, K_OTHER, 0.0, 16.0 * (double)k * n);
@@ -401,7 +420,12 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   // 4. Z1 = A V (the one extra pass over A)
   {
     KTimer kt(h, K_INNER, 2.0 * (double)m * n * k, 8.0 * ((double)m * n + (double)n * k + (double)m * k));
-    RQ_CHECK(h, launch_gemm_nn(Z1, m, (int)m, (int)k, Ad, lda, V, ldv, (int)n, 1.0, 0.0, s));
+    if (f32)
+      RQ_CHECK(h, launch_gemm_nn_bf16(Z1, m, (int)m, (int)k, static_cast<const float*>(A), lda, V,
+                                      ldv, (int)n, s));
+    else
+      RQ_CHECK(h, launch_gemm_nn(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda, V, ldv,
+                                 (int)n, 1.0, 0.0, s));
   }
   // 5. QR of Z1: U = Q[:, 0:k], X = upper factor
   RQ_TRY(qr_blocked(h, Z1, m, m, k, tauq, Tb2, w));
