@@ -220,6 +220,69 @@ int32_t rq_profile_count(rq_handle h);
 rq_status rq_profile_get(rq_handle h, int32_t index, const char** name, int64_t* launches,
                          double* total_ms, double* flops, double* bytes);
 
+/*
+ * Serving loop: continuous batching of TRQRCP / TUXV requests of uneven sizes
+ * on one device (not part of the paper; its truncated routines are the work).
+ *
+ * rq_serve_start creates `slots` execution slots, each with its own HIP stream
+ * and library handle whose workspace is reserved for requests up to
+ * max_m x max_n with rank <= max_k and b + p <= max_ell, plus one device arena
+ * of budget_bytes for request data (A, Omega and the outputs).  A scheduler
+ * thread admits queued requests in arrival order whenever a slot is free and a
+ * contiguous block of the request's footprint fits in the arena (a request
+ * larger than the whole arena is rejected at submit time); admitted requests
+ * run concurrently on their slots, so work from different requests overlaps on
+ * the device.  Each request is computed exactly as by trqrcp_truncate /
+ * tuxv_svd on its own, so results do not depend on what else is running.
+ *
+ * Request data lives in host memory owned by the caller, which must stay valid
+ * until the request completes: A (m x n, column-major, leading dimension m;
+ * float for RQ_MIXED_BF16, double for RQ_FP64) and Omega (ell x m, leading
+ * dimension ell) are copied in (page-locked memory keeps the copies
+ * asynchronous); outputs are copied back to non-NULL host pointers:
+ *   TRQRCP: jpvt[n], out0 = Y (m x k), out1 = T (k x k), out2 = R (k x n);
+ *   TUXV:   jpvt[n], out0 = U (m x k), out1 = X (k x k), out2 = V (n x k).
+ * Latency runs from rq_serve_submit to the moment the scheduler sees the
+ * request's completion event (host copies included).
+ * rq_serve_stop finishes every submitted request, then frees everything.
+ * Errors: -i for invalid argument i, RQ_E_UNSUPPORTED for a request beyond the
+ * reserved shape or larger than the arena, RQ_E_NOMEM, RQ_E_HIP.
+ */
+typedef struct rq_server_s* rq_server;
+
+enum { RQ_OP_TRQRCP = 0, RQ_OP_TUXV = 1 };
+enum { RQ_REQ_QUEUED = 0, RQ_REQ_RUNNING = 1, RQ_REQ_DONE = 2, RQ_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t op;             /* RQ_OP_TRQRCP or RQ_OP_TUXV                    */
+  int32_t prec;           /* rq_prec                                       */
+  int64_t m, n, k, b, p;  /* as trqrcp_truncate                            */
+  const void* A;          /* host, m x n                                   */
+  const double* Omega;    /* host, (b + p) x m                             */
+  int64_t* jpvt;          /* host outputs (NULL: not copied back)          */
+  double* out0;
+  double* out1;
+  double* out2;
+} rq_request;
+
+typedef struct {
+  int32_t state;          /* RQ_REQ_*                                      */
+  int32_t status;         /* rq_status of the request                      */
+  int64_t device_error;   /* RQ_DEV_* bits seen by the request's slot      */
+  double queue_ms;        /* submit -> admission                           */
+  double latency_ms;      /* submit -> completion observed                 */
+  double flops;           /* algorithmic flop count of the request         */
+} rq_result;
+
+rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t max_m,
+                         int64_t max_n, int64_t max_k, int64_t max_ell, rq_server* server);
+rq_status rq_serve_submit(rq_server server, const rq_request* req, uint64_t* id);
+rq_status rq_serve_poll(rq_server server, uint64_t id, rq_result* result);
+rq_status rq_serve_wait(rq_server server, uint64_t id, rq_result* result);
+rq_status rq_serve_stats(rq_server server, int64_t* completed, int64_t* peak_bytes,
+                         int32_t* peak_running);
+rq_status rq_serve_stop(rq_server server);
+
 #ifdef __cplusplus
 }
 #endif

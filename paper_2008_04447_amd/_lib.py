@@ -39,7 +39,35 @@ SIGNATURES = {
                                         ctypes.POINTER(c_i64), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
+    "rq_serve_start": (ctypes.c_int32, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32, c_i64, c_i64,
+                                        c_i64, c_i64, ctypes.POINTER(c_p)]),
+    "rq_serve_submit": (ctypes.c_int32, [c_p, c_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "rq_serve_poll": (ctypes.c_int32, [c_p, ctypes.c_uint64, c_p]),
+    "rq_serve_wait": (ctypes.c_int32, [c_p, ctypes.c_uint64, c_p]),
+    "rq_serve_stats": (ctypes.c_int32, [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "rq_serve_stop": (ctypes.c_int32, [c_p]),
 }
+
+
+class Request(ctypes.Structure):
+    """Mirror of rq_request (include/rqrcp.h)."""
+    _fields_ = [("op", ctypes.c_int32), ("prec", ctypes.c_int32), ("m", c_i64), ("n", c_i64),
+                ("k", c_i64), ("b", c_i64), ("p", c_i64), ("A", c_p), ("Omega", c_p),
+                ("jpvt", c_p), ("out0", c_p), ("out1", c_p), ("out2", c_p)]
+
+
+class Result(ctypes.Structure):
+    """Mirror of rq_result (include/rqrcp.h)."""
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("device_error", c_i64),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+RQ_OP_TRQRCP = 0
+RQ_OP_TUXV = 1
+RQ_REQ_DONE = 2
+RQ_REQ_FAILED = 3
 
 RQ_OK = 0
 RQ_E_HIP = 1001

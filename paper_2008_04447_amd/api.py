@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -187,3 +188,76 @@ def sample_qrcp(B, steps, handle=None):
     rc = _lib.load().rq_sample_qrcp(h.ptr, ell, n, steps, _ptr(B), ld(B), _ptr(perm))
     _check("rq_sample_qrcp", rc, h)
     return perm
+
+
+# ----------------------------------------------------------------------------- serving
+def pinned_empty(shape, dtype):
+    """Page-locked host array in column-major order (asynchronous copies)."""
+    tdt = {np.float32: torch.float32, np.float64: torch.float64, np.int64: torch.int64}[dtype]
+    if len(shape) == 2:
+        t = torch.empty((shape[1], shape[0]), dtype=tdt, pin_memory=True).t()
+    else:
+        t = torch.empty(shape, dtype=tdt, pin_memory=True)
+    return t.numpy()
+
+
+class Server:
+    """Continuous-batching server over rq_serve_* (requests in host memory)."""
+
+    def __init__(self, budget_bytes, slots, max_m, max_n, max_k, max_ell, device=0):
+        lib = _lib.load()
+        self.ptr = ctypes.c_void_p()
+        _check("rq_serve_start", lib.rq_serve_start(device, int(budget_bytes), slots, max_m, max_n,
+                                                    max_k, max_ell, ctypes.byref(self.ptr)))
+        self._keep = {}
+
+    def submit(self, op, A, Omega, b, p, k, outputs=True):
+        """A, Omega: column-major host arrays (float32 A = mixed BF16, float64 A = FP64)."""
+        lib = _lib.load()
+        m, n = A.shape
+        if not A.flags.f_contiguous or not Omega.flags.f_contiguous:
+            raise ValueError("A and Omega must be column-major (Fortran order)")
+        prec = RQ_MIXED_BF16 if A.dtype == np.float32 else RQ_FP64
+        outs = None
+        if outputs:
+            if op == _lib.RQ_OP_TRQRCP:
+                outs = (pinned_empty((n,), np.int64), pinned_empty((m, k), np.float64),
+                        pinned_empty((k, k), np.float64), pinned_empty((k, n), np.float64))
+            else:
+                outs = (pinned_empty((n,), np.int64), pinned_empty((m, k), np.float64),
+                        pinned_empty((k, k), np.float64), pinned_empty((n, k), np.float64))
+        req = _lib.Request(op, prec, m, n, k, b, p, A.ctypes.data, Omega.ctypes.data,
+                           outs[0].ctypes.data if outs else None,
+                           outs[1].ctypes.data if outs else None,
+                           outs[2].ctypes.data if outs else None,
+                           outs[3].ctypes.data if outs else None)
+        rid = ctypes.c_uint64()
+        rc = lib.rq_serve_submit(self.ptr, ctypes.byref(req), ctypes.byref(rid))
+        if rc != 0:
+            raise RQError("rq_serve_submit", rc)
+        self._keep[rid.value] = (A, Omega, outs)
+        return rid.value
+
+    def _result(self, fn, rid):
+        res = _lib.Result()
+        _check(fn.__name__, fn(self.ptr, rid, ctypes.byref(res)))
+        d = {f: getattr(res, f) for f, _ in _lib.Result._fields_}
+        d["outputs"] = self._keep.get(rid, (None, None, None))[2]
+        return d
+
+    def poll(self, rid):
+        return self._result(_lib.load().rq_serve_poll, rid)
+
+    def wait(self, rid):
+        return self._result(_lib.load().rq_serve_wait, rid)
+
+    def stats(self):
+        c, pb, pr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check("rq_serve_stats", _lib.load().rq_serve_stats(self.ptr, ctypes.byref(c),
+                                                             ctypes.byref(pb), ctypes.byref(pr)))
+        return {"completed": c.value, "peak_bytes": pb.value, "peak_running": pr.value}
+
+    def stop(self):
+        if self.ptr:
+            _check("rq_serve_stop", _lib.load().rq_serve_stop(self.ptr))
+            self.ptr = ctypes.c_void_p()

@@ -150,5 +150,7 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt);
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
                             const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat);
+// Workspace bytes trqrcp_truncate / tuxv_svd reserve for a problem shape.
+size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv);
 
 }  // namespace rq

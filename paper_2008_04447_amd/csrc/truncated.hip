@@ -323,6 +323,15 @@ static rq_status form_q(rq_handle h, const double* A, int64_t lda, int64_t M, in
   return RQ_OK;
 }
 
+size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv) {
+  size_t w = trwork_doubles(m, n, k, ell);
+  if (tuxv)
+    w += padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) + padded_bytes((size_t)k * n) +
+         padded_bytes((size_t)n * k) + padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
+         padded_bytes((size_t)k + 64);
+  return w;
+}
+
 static rq_status check_common(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
                               int64_t b, int64_t p, const void* A, int64_t lda,
                               const double* Omega, int64_t ldo) {
