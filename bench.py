@@ -195,6 +195,226 @@ def bench_rqrcp(args):
     return res
 
 
+def trqrcp_flops(m, n, k, b, p):
+    """Algorithmic flops of TRQRCP: sketch, per block Y2^T A, R rows, selected
+    columns, panel, small products, sample update."""
+    ell = b + p
+    f = 2.0 * ell * m * n
+    c0 = 0
+    while c0 < k:
+        bj = min(b, k - c0)
+        M, N = m - c0, n - c0
+        Nt = N - bj
+        f += 2.0 * bj * M * Nt + 2.0 * bj * (c0 + bj) * Nt + 2.0 * M * bj * c0 + 2.0 * M * bj * bj
+        f += 2.0 * bj * M * c0 + 2.0 * bj * c0 * Nt + 2.0 * bj * bj * Nt
+        c0 += bj
+    return f
+
+
+def _gpu_mem_clear():
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def _timed(fn, steps, warmup, h):
+    import torch
+    from paper_2008_04447_amd import _lib
+    lib = _lib.load()
+    for _ in range(warmup):
+        fn()
+        h.sync()
+    lib.rq_profile_start(h.ptr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.rq_profile_stop(h.ptr)
+    h.sync()
+    return (t1 - t0) * 1e3 / steps, out, profile_table(h)
+
+
+def bench_trqrcp_c3(args):
+    """Mixed-precision TRQRCP, rank 512, on a 20000 x 20000 FP32 matrix with
+    sigma_i = exp(-i/200) (only sigma_i > 1e-9, i < 4145, is drawn: the rest is
+    below FP32 resolution).  Error vs the library's own FP64 TRQRCP on the same
+    matrix (which the parity tests pin to the FP64 oracle)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2008_04447_amd import api
+    m = n = 20000
+    k, b, p = 512, 64, 8
+    dev = torch.device("cuda", 0)
+    sig = synth.spectrum("exp", 4145, scale=200.0)
+    log("C3: drawing A 20000x20000 (exp(-i/200)) on the GPU")
+    A64 = synth.low_rank_device(m, n, sig, synth.seed_for(2, "U"), dev)
+    A32 = torch.empty((n, m), dtype=torch.float32, device=dev).t()
+    A32.copy_(A64)
+    A64.copy_(A32)                              # the FP64 run sees the same FP32 values
+    om = api.colmajor(synth.omega(b + p, m, synth.seed_for(2, "Omega")), device=dev)
+    h = api.default_handle(0)
+    ms, out, prof = _timed(lambda: api.trqrcp_truncate(A32, om, b, p, k, handle=h), args.c3_steps, 1, h)
+    ms64, out64, _ = _timed(lambda: api.trqrcp_truncate(A64, om, b, p, k, handle=h), 1, 1, h)
+
+    def err(o):
+        jp, Y, T, R = o
+        ap = A64[:, jp]
+        qk = -(Y @ (T @ Y[:k, :].T))            # Q[:, :k] = I[:, :k] - Y T Y_1^T
+        qk[:k, :] += torch.eye(k, dtype=torch.float64, device=dev)
+        return float(torch.linalg.norm(ap - qk @ R) / torch.linalg.norm(A64))
+    e32, e64 = err(out), err(out64)
+    opt = float(np.sqrt(np.sum(sig[k:] ** 2) / np.sum(sig ** 2)))
+    fl = trqrcp_flops(m, n, k, b, p)
+    roof = roofline(prof, args.c3_steps)
+    res = {"ms_per_step": round(ms, 3), "value": round(fl / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
+           "dtype": "bf16-mfma/fp32-acc, fp64 panel", "fp64_ms_per_step": round(ms64, 3),
+           "trunc_error": e32, "trunc_error_fp64": e64, "error_ratio": round(e32 / e64, 5),
+           "optimal_svd_error": opt, "flops_per_step": fl, "roofline": roof,
+           "kernels_ms_per_step": {kk: round(v["ms"] / args.c3_steps, 3) for kk, v in prof.items()},
+           "config": {"workload": "trqrcp_mixed_20000x20000_exp200", "m": m, "n": n, "k": k, "b": b,
+                      "p": p}}
+    log(f"C3: {ms:.2f} ms/step ({res['value']} TFLOP/s), error {e32:.5e} vs fp64 {e64:.5e} "
+        f"ratio {e32 / e64:.4f}")
+    del A64, A32, out, out64
+    _gpu_mem_clear()
+    return res
+
+
+def bench_tuxv_c4(args):
+    """Mixed-precision TUXV, rank 256, on 50000 x 8000 FP32:
+    U diag((i+1)^-1.5) V^T + N(0, 1e-12) noise (std 1e-6)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2008_04447_amd import api
+    m, n, k, b, p = 50000, 8000, 256, 64, 8
+    dev = torch.device("cuda", 0)
+    sig = synth.spectrum("poly", n, power=1.5)
+    log("C4: drawing A 50000x8000 ((i+1)^-1.5 + noise) on the GPU")
+    A64 = synth.low_rank_device(m, n, sig, synth.seed_for(3, "U"), dev)
+    A64 += synth.gaussian_device(m, n, synth.seed_for(3, "noise"), dev, std=1e-6)
+    A32 = torch.empty((n, m), dtype=torch.float32, device=dev).t()
+    A32.copy_(A64)
+    A64.copy_(A32)
+    om = api.colmajor(synth.omega(b + p, m, synth.seed_for(3, "Omega")), device=dev)
+    h = api.default_handle(0)
+    ms, out, prof = _timed(lambda: api.tuxv_svd(A32, om, b, p, k, handle=h), args.c4_steps, 1, h)
+    ms64, out64, _ = _timed(lambda: api.tuxv_svd(A64, om, b, p, k, handle=h), 1, 1, h)
+
+    def err(o):
+        U, X, V, _ = o
+        return float(torch.linalg.norm(A64 - U @ (X @ V.T)) / torch.linalg.norm(A64))
+    e32, e64 = err(out), err(out64)
+    s32 = torch.linalg.svdvals(out[1]).cpu().numpy()
+    s64 = torch.linalg.svdvals(out64[1]).cpu().numpy()
+    rel = np.abs(s32 - s64) / s64
+    fl = trqrcp_flops(m, n, k, b, p) + 2.0 * m * n * k + 8.0 * (m + n) * k * k
+    roof = roofline(prof, args.c4_steps)
+    res = {"ms_per_step": round(ms, 3), "value": round(fl / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
+           "dtype": "bf16-mfma/fp32-acc, fp64 panel", "fp64_ms_per_step": round(ms64, 3),
+           "approx_error": e32, "approx_error_fp64": e64, "error_ratio": round(e32 / e64, 5),
+           "sigma_rel_err_median": float(np.median(rel)), "sigma_rel_err_max": float(rel.max()),
+           "sigma_rel_err_median_top64": float(np.median(rel[:64])),
+           "flops_per_step": fl, "roofline": roof,
+           "kernels_ms_per_step": {kk: round(v["ms"] / args.c4_steps, 3) for kk, v in prof.items()},
+           "config": {"workload": "tuxv_mixed_50000x8000_poly1.5_noise1e-6", "m": m, "n": n, "k": k,
+                      "b": b, "p": p}}
+    log(f"C4: {ms:.2f} ms/step ({res['value']} TFLOP/s), error ratio {e32 / e64:.4f}, "
+        f"sigma rel err median {np.median(rel):.2e}")
+    del A64, A32, out, out64
+    _gpu_mem_clear()
+    return res
+
+
+def bench_serve_c5(args):
+    """Serving: Poisson arrivals (mean 200/s) of TRQRCP / TUXV requests (50/50),
+    m, n ~ U[256, 4096], k ~ U{16,32,64,128,256}, b = min(64, k), p = 8, FP32
+    A = U diag(10^(-i/50)) V^T (only sigma_i >= 1e-9, i < 450, is drawn), Omega
+    seeded per request.  A pool of distinct matrices is drawn up front into
+    page-locked host memory and requests cycle through it."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2008_04447_amd import api
+    rng = synth.rng(synth.seed_for(4, "perm"))
+    dev = torch.device("cuda", 0)
+    n_warm, n_req, rate = args.serve_warmup, args.serve_requests, args.serve_rate
+    pool = []
+    log(f"C5: drawing {args.serve_pool} request matrices")
+    for i in range(args.serve_pool):
+        m = int(rng.integers(256, 4097))
+        n = int(rng.integers(256, 4097))
+        r = min(m, n, 450)
+        sig = synth.spectrum("pow10", r, scale=50.0)
+        a = synth.low_rank_device(m, n, sig, synth.seed_for(4, "U") + 17 * i, dev, torch.float32)
+        host = api.pinned_empty((m, n), np.float32)
+        host[:] = a.cpu().numpy()
+        pool.append(host)
+        del a
+    _gpu_mem_clear()
+    total = n_warm + n_req
+    ks = rng.choice([16, 32, 64, 128, 256], size=total)
+    ops = rng.integers(0, 2, size=total)
+    gaps = rng.exponential(1.0 / rate, size=total)
+    log(f"C5: drawing {total} per-request Omega into page-locked memory")
+    oms = []
+    for i in range(total):
+        m = pool[i % len(pool)].shape[0]
+        b = min(64, int(min(ks[i], m, pool[i % len(pool)].shape[1])))
+        om = api.pinned_empty((b + 8, m), np.float64)
+        om[:] = synth.omega(b + 8, m, synth.seed_for(4, "Omega") + i)
+        oms.append(om)
+    srv = api.Server(args.serve_budget_gb * (1 << 30), slots=args.serve_slots, max_m=4096, max_n=4096,
+                     max_k=256, max_ell=72)
+    flops = 0.0
+    lat, ids = [], []
+    try:
+        t_next = time.perf_counter()
+        t_first = None
+        for i in range(total):
+            a = pool[i % len(pool)]
+            m, n = a.shape
+            k = int(min(ks[i], m, n))
+            b = min(64, k)
+            om = oms[i]
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                time.sleep(min(5e-4, max(0.0, t_next - time.perf_counter())))
+            if i == n_warm:
+                t_first = time.perf_counter()
+            ids.append(srv.submit(int(ops[i]), a, om, b, 8, k, outputs=False))
+            if i % 500 == 0:
+                log(f"C5: submitted {i}/{total}")
+        res_all = [srv.wait(x) for x in ids]
+        t_last = time.perf_counter()
+        st = srv.stats()
+    finally:
+        srv.stop()
+    timed = res_all[n_warm:]
+    bad = [r for r in timed if r["state"] != 2 or r["status"] != 0]
+    lat = np.array([r["latency_ms"] for r in timed])
+    q = np.array([r["queue_ms"] for r in timed])
+    flops = float(sum(r["flops"] for r in timed))
+    span = t_last - t_first
+    res = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "mean_ms": round(float(lat.mean()), 3), "queue_p99_ms": round(float(np.percentile(q, 99)), 3),
+           "requests": n_req, "warmup_requests": n_warm, "rate_per_s": rate,
+           "achieved_rate_per_s": round(n_req / span, 2), "aggregate_tflops": round(flops / span / 1e12, 5),
+           "failed": len(bad), "slots": args.serve_slots, "budget_gb": args.serve_budget_gb,
+           "peak_running": st["peak_running"], "peak_bytes": st["peak_bytes"],
+           "config": {"workload": "serve_trqrcp_tuxv_poisson200_m256-4096_fp32",
+                      "pool_matrices": len(pool)}}
+    log(f"C5: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms, {res['aggregate_tflops']} TFLOP/s, "
+        f"peak running {st['peak_running']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,12 +424,34 @@ def main():
     ap.add_argument("--cpu-k", type=int, default=512, help="pivots of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-QRCP comparison")
+    ap.add_argument("--skip", default="", help="comma list of secondary workloads to skip: "
+                    "trqrcp,tuxv,serving")
+    ap.add_argument("--c3-steps", type=int, default=3)
+    ap.add_argument("--c4-steps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=int, default=8)
     args = ap.parse_args()
+    args.skip = [x for x in args.skip.split(",") if x]
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     res = bench_rqrcp(args)
+    secondary = {}
+    for name, fn in (("trqrcp_mixed_20000", bench_trqrcp_c3), ("tuxv_mixed_50000x8000", bench_tuxv_c4),
+                     ("serving", bench_serve_c5)):
+        if name.split("_")[0] in args.skip:
+            continue
+        try:
+            secondary[name] = fn(args)
+        except Exception as e:          # report, keep the headline line intact
+            log(f"{name} failed: {type(e).__name__}: {e}")
+            secondary[name] = {"error": f"{type(e).__name__}: {e}"}
+    res["secondary"] = secondary
     print(json.dumps(res), flush=True)
 
 

@@ -126,3 +126,39 @@ def workload(config: int, small: bool = False):
         3: dict(m=50000, n=8000, b=64, p=8, k=256),
     }
     return dict(table[config])
+
+
+def low_rank_device(m, n, sigma, seed, device, dtype_out=None):
+    """Large low-rank inputs drawn on a GPU: A = U diag(sigma) V^T with Haar U
+    (m x r) and V (n x r), r = len(sigma), built in float64 with torch's seeded
+    device generator (Mezzadri's sign-corrected QR, as ``haar``).  Only the
+    first r singular values are drawn, so callers pass the part of the spectrum
+    that is visible at the output precision.  Returns a column-major tensor."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    r = len(sigma)
+    s = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+
+    def haar_t(rows):
+        x = torch.randn((rows, r), generator=g, dtype=torch.float64, device=device)
+        q, rr = torch.linalg.qr(x, mode="reduced")
+        d = torch.sign(torch.diagonal(rr))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+
+    u = haar_t(m)
+    v = haar_t(n)
+    a = (u * s[None, :]) @ v.T
+    del u, v
+    out = torch.empty((n, m), dtype=dtype_out or torch.float64, device=device).t()
+    out.copy_(a)
+    return out
+
+
+def gaussian_device(m, n, seed, device, std=1.0):
+    """i.i.d. N(0, std^2) m x n float64 tensor (column-major) from a seeded device generator."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return (torch.randn((n, m), generator=g, dtype=torch.float64, device=device) * std).t()
