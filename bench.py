@@ -434,8 +434,19 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
     args.skip = [x for x in args.skip.split(",") if x]
+    if args.copy_calibration:
+        import torch
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            x.copy_(y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_call": 8 << 27, "calls": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
