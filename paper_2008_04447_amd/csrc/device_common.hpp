@@ -70,30 +70,99 @@ RQ_DEV bool prior_timeout(const int64_t* status) {
                     kErrTimeout);
 }
 
-RQ_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-
 // (value, position) maximum: larger value wins, equal values -> lower position.
 // NaN values never win (comparisons with NaN are false).
 RQ_DEV bool better(double v1, int p1, double v2, int p2) {
   return v1 > v2 || (v1 == v2 && p1 < p2);
 }
 
+// ---- cross-lane reductions ----------------------------------------------------
+// Built from DPP row moves (quad_perm, row_half_mirror, row_mirror), which read
+// a neighbour's register directly instead of going through the LDS crossbar,
+// and v_readlane across the four rows of 16 lanes.  Every lane of the group
+// combined must be active.  Each stage pairs lanes symmetrically and addition
+// is commutative, so every lane of the group ends with bitwise the same value.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16 lanes
+
+template <int kCtrl>
+RQ_DEV int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int kCtrl>
+RQ_DEV double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_i32<kCtrl>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_i32<kCtrl>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+RQ_DEV double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 4 lanes of a quad.
+RQ_DEV double quad_sum(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  return v;
+}
+
+// Sum over a row of 16 lanes (lanes 16r .. 16r + 15).
+RQ_DEV double row16_sum(double v) {
+  v = quad_sum(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  return v;
+}
+
+// Sum over the wave; the result is wave-uniform.
+RQ_DEV double wave_sum(double v) {
+  v = row16_sum(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+template <int kCtrl>
+RQ_DEV void argmax_step(double& v, int& p, int& who) {
+  const double v2 = dpp_f64<kCtrl>(v);
+  const int p2 = dpp_i32<kCtrl>(p);
+  const int w2 = dpp_i32<kCtrl>(who);
+  if (better(v2, p2, v, p)) {
+    v = v2;
+    p = p2;
+    who = w2;
+  }
+}
+
+// Wave-wide (value, position) maximum with a payload `who`; every lane gets
+// the winner.  Positions of real candidates are distinct, so the winner does
+// not depend on the order in which candidates meet.
 RQ_DEV void wave_argmax(double& v, int& p, int& who) {
+  argmax_step<kDppXor1>(v, p, who);
+  argmax_step<kDppXor2>(v, p, who);
+  argmax_step<kDppHalfMirror>(v, p, who);
+  argmax_step<kDppMirror>(v, p, who);
+  double bv = readlane_f64(v, 0);
+  int bp = __builtin_amdgcn_readlane(p, 0), bw = __builtin_amdgcn_readlane(who, 0);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double v2 = __shfl_xor(v, o, kWave);
-    int p2 = __shfl_xor(p, o, kWave);
-    int w2 = __shfl_xor(who, o, kWave);
-    if (better(v2, p2, v, p)) {
-      v = v2;
-      p = p2;
-      who = w2;
+  for (int r = 16; r < 64; r += 16) {
+    const double v2 = readlane_f64(v, r);
+    const int p2 = __builtin_amdgcn_readlane(p, r), w2 = __builtin_amdgcn_readlane(who, r);
+    if (better(v2, p2, bv, bp)) {
+      bv = v2;
+      bp = p2;
+      bw = w2;
     }
   }
+  v = bv;
+  p = bp;
+  who = bw;
 }
 
 typedef double dx4 __attribute__((ext_vector_type(4)));

@@ -21,13 +21,6 @@ constexpr int kSqCols = kSqThreads / kQ;       // columns per workgroup
 constexpr int kSqWaves = kSqThreads / 64;
 constexpr int kSpecCap = 8192;                 // doubles of LDS for the one-round candidate fetch
 
-// Sum over the 4 lanes of a quad; every lane of the quad gets the same bits.
-RQ_DEV double quad_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  return v;
-}
-
 template <int LM>
 __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   constexpr int RPL = LM / kQ;                 // rows per lane
@@ -41,13 +34,9 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   const bool own = c < a.N;
   if (prior_timeout(a.status)) return;
 
-  __shared__ double s_v[LM];
-  __shared__ double s_col[LM];
   __shared__ double s_wv[kSqWaves];
   __shared__ int s_wp[kSqWaves], s_ww[kSqWaves];
   __shared__ double s_all[kSpecCap];
-  __shared__ double s_tau, s_beta, s_best;
-  __shared__ int s_owner, s_bestpos, s_winwg, s_winpos;
 
   double x[RPL];
 #pragma unroll
@@ -72,7 +61,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   bool flagged = false;
 
   for (int j = 0; j < a.steps; ++j) {
-    // ---- local best candidate --------------------------------------------
+    // ---- local best candidate: wave reduction, then every wave reduces the
+    // 16 wave winners itself (no single-thread pass, no extra barrier) -------
     const bool lead = active && q == 0;
     double bv = lead ? nu2 : -1.0;
     int bp = lead ? pos : INT_MAX;
@@ -88,30 +78,22 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       s_ww[wave] = who;
     }
     __syncthreads();
-    if (t == 0) {
-      double v = s_wv[0];
-      int p = s_wp[0], w = s_ww[0];
-      for (int k = 1; k < kSqWaves; ++k)
-        if (better(s_wv[k], s_wp[k], v, p)) {
-          v = s_wv[k];
-          p = s_wp[k];
-          w = s_ww[k];
-        }
-      s_best = v;
-      s_bestpos = p;
-      s_owner = (p == INT_MAX) ? -1 : w;
-    }
-    __syncthreads();
-    if (cl == s_owner) {
+    {
+      double v = (lane < kSqWaves) ? s_wv[lane] : -1.0;
+      int p = (lane < kSqWaves) ? s_wp[lane] : INT_MAX;
+      int w = (lane < kSqWaves) ? s_ww[lane] : 0;
+      wave_argmax(v, p, w);
+      const int owner = (p == INT_MAX) ? -1 : w;
+      double* rec = a.rec + ((int64_t)(j & 1) * a.nwg + wg) * a.rs;
+      if (cl == owner) {
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) s_col[q + kQ * i] = x[i];
-    }
-    __syncthreads();
-    double* rec = a.rec + ((int64_t)(j & 1) * a.nwg + wg) * a.rs;
-    if (t < LM) rec[2 + t] = (s_owner >= 0) ? s_col[t] : 0.0;
-    if (t == 0) {
-      rec[0] = s_best;
-      rec[1] = (double)s_bestpos;
+        for (int i = 0; i < RPL; ++i) rec[2 + q + kQ * i] = x[i];
+      }
+      if (owner < 0 && t < LM) rec[2 + t] = 0.0;
+      if (t == 0) {
+        rec[0] = v;
+        rec[1] = (double)p;
+      }
     }
     // ---- exchange ----------------------------------------------------------
     if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, (uint32_t)j, a.status)) return;
@@ -119,8 +101,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
     // all candidates (value, position) and, when they fit in LDS, their columns,
     // fetched in one round of independent loads
     const bool spec = a.nwg * (LM + 2) <= kSpecCap;
+    const int per = spec ? LM + 2 : 2;
     if (spec) {
-      const int per = LM + 2;
       for (int e = t; e < a.nwg * per; e += kSqThreads) {
         const int w = e / per, f = e - w * per;
         s_all[e] = rj[(int64_t)w * a.rs + f];
@@ -132,8 +114,9 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
     }
     __syncthreads();
-    if (wave == 0) {
-      const int per = spec ? LM + 2 : 2;
+    // every wave finds the same winner and forms the same reflector
+    int wwg = 0, wpos;
+    {
       double v = -1.0;
       int p = INT_MAX, w = 0;
       for (int i = lane; i < a.nwg; i += 64) {
@@ -146,46 +129,36 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
         }
       }
       wave_argmax(v, p, w);
-      if (lane == 0) {
-        s_winpos = p;
-        s_winwg = w;
-      }
+      wpos = p;
+      wwg = w;
     }
-    __syncthreads();
-    const int wpos = s_winpos;
     if (wpos == INT_MAX) {          // every workgroup sees the same: consistent exit
       if (t == 0 && wg == 0) raise_status(a.status, kErrNoPivot);
       return;
     }
-    if (t < LM)
-      s_col[t] = spec ? s_all[s_winwg * (LM + 2) + 2 + t] : rj[(int64_t)s_winwg * a.rs + 2 + t];
-    __syncthreads();
-    // ---- Householder vector of the winner (wave 0) ----------------------------
-    if (wave == 0) {
-      double s2 = 0.0;
-      if (lane >= j && lane < LM) s2 += s_col[lane] * s_col[lane];
-      if (lane + 64 >= j && lane + 64 < LM) s2 += s_col[lane + 64] * s_col[lane + 64];
-      s2 = wave_sum(s2);
-      const double alpha = s_col[j];
-      double beta = 0.0, tau = 0.0, scale = 0.0;
-      if (s2 > 0.0) {
-        const double sn = sqrt(s2);
-        beta = (alpha >= 0.0) ? -sn : sn;
-        scale = 1.0 / (alpha - beta);
-        tau = (beta - alpha) / beta;
-      }
-      for (int r = lane; r < LM; r += 64) s_v[r] = (r < j) ? 0.0 : (r == j ? 1.0 : s_col[r] * scale);
-      if (lane == 0) {
-        s_tau = tau;
-        s_beta = beta;
-      }
+    if (!spec) {
+      // columns did not fit: fetch the winner's column into the front of s_all
+      __syncthreads();
+      if (t < LM) s_all[2 + t] = rj[(int64_t)wwg * a.rs + 2 + t];
+      __syncthreads();
+      wwg = 0;
     }
-    __syncthreads();
-    const double tau = s_tau;
+    const double* col = s_all + (spec ? wwg * (LM + 2) : 0) + 2;   // winner's column in LDS
+    double s2 = 0.0;
+    if (lane >= j && lane < LM) s2 += col[lane] * col[lane];
+    if (lane + 64 >= j && lane + 64 < LM) s2 += col[lane + 64] * col[lane + 64];
+    s2 = wave_sum(s2);
+    const double alpha = col[j];
+    double beta = 0.0, tau = 0.0, scale = 0.0;
+    if (s2 > 0.0) {
+      const double sn = sqrt(s2);
+      beta = (alpha >= 0.0) ? -sn : sn;
+      scale = 1.0 / (alpha - beta);
+      tau = (beta - alpha) / beta;
+    }
     // ---- positions: j <-> wpos ----------------------------------------------
     if (active) {
       if (pos == wpos) {
-        const double beta = s_beta;
         pos = j;
         active = false;
 #pragma unroll
@@ -203,7 +176,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        v[i] = s_v[q + kQ * i];
+        const int r = q + kQ * i;
+        v[i] = (r < j) ? 0.0 : (r == j ? 1.0 : col[r] * scale);
         if (i & 1)
           d1 += v[i] * x[i];
         else
@@ -222,7 +196,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
       nu2 = quad_sum(n0 + n1);
     }
-    __syncthreads();   // s_v / s_col are rewritten in the next step
+    __syncthreads();   // s_all and the wave winners are rewritten in the next step
   }
   // Every workgroup loaded its columns before the first barrier, so the
   // in-place write of the permuted sample cannot overwrite unread input.
