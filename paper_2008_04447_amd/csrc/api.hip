@@ -38,10 +38,11 @@ static hipEvent_t next_event(rq_handle h) {
   return e;
 }
 
-KTimer::KTimer(rq_handle h_, int cls_, double f_, double b_) : h(h_), cls(cls_), f(f_), b(b_) {
+KTimer::KTimer(rq_handle h_, int cls_, double f_, double b_, hipStream_t s_)
+    : h(h_), cls(cls_), f(f_), b(b_), s(s_) {
   if (h->prof) {
     e0 = next_event(h);
-    if (e0) (void)hipEventRecord(e0, h->stream);
+    if (e0) (void)hipEventRecord(e0, s);
   }
 }
 
@@ -49,20 +50,20 @@ KTimer::~KTimer() {
   if (!e0) return;
   hipEvent_t e1 = next_event(h);
   if (!e1) return;
-  (void)hipEventRecord(e1, h->stream);
+  (void)hipEventRecord(e1, s);
   h->recs.push_back(ProfRec{cls, e0, e1, f, b});
 }
 
 size_t sketch_part_doubles(int ell, int64_t m, int64_t n) {
   int ks, kc;
-  plan_split((int)m, (int)n, &ks, &kc);
+  plan_split((int)m, (int)n, &ks, &kc, ell);
   return ks > 1 ? (size_t)ks * ell * n : 0;
 }
 
 rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
                       const double* A, int64_t lda, double* B, int64_t ldb, double* part) {
   int ks, kc;
-  plan_split((int)m, (int)n, &ks, &kc);
+  plan_split((int)m, (int)n, &ks, &kc, ell);
   GemmArgs g{};
   g.L = Omega;
   g.sLp = 1;
@@ -158,7 +159,7 @@ rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* 
 
 size_t sq_rec_doubles(int ell, int64_t N) {
   const int lm = sq_lm(ell);
-  return (size_t)2 * ((N + 255) / 256) * sq_record_stride(lm);
+  return (size_t)2 * sq_max_groups(N) * sq_record_stride(lm);
 }
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
@@ -170,7 +171,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.ell = ell;
   a.N = (int)N;
   a.steps = steps;
-  a.nwg = (int)((N + 255) / 256);
+  a.nwg = sq_groups(N, h->max_groups);
   a.rec = w.rec;
   a.rs = sq_record_stride(lm);
   a.counter = h->sync;
@@ -275,6 +276,12 @@ rq_status rq_destroy(rq_handle h) {
   if (!h) return -1;
   DeviceGuard guard(h->device);
   (void)hipStreamSynchronize(h->stream);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->ev_z) (void)hipEventDestroy(h->ev_z);
+  if (h->ev_u) (void)hipEventDestroy(h->ev_u);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->status) (void)hipFree(h->status);
@@ -454,6 +461,13 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   sw.src_top = cv.take<int>(64);
   sw.dst_low = cv.take<int>(64);
 
+  if (!h->side) {
+    RQ_CHECK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_z, hipEventDisableTiming));
+    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_u, hipEventDisableTiming));
+  }
+  bool pending_rows = false;
+
   // ---- B = Omega A -------------------------------------------------------------
   RQ_TRY(sketch_fp64(h, (int)ell, m, n, Omega, ldo, A, lda, sample, ell, part));
   RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
@@ -465,6 +479,11 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     double* Ablk = A + col0 + col0 * lda;            // trailing block A(col0:, col0:)
     // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
     RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr));
+    // the previous block's update of rows below its R12 must be complete
+    if (pending_rows) {
+      RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
+      pending_rows = false;
+    }
     // 2. permute all m rows of A's columns col0.. (finished R rows included), jpvt
     {
       KTimer kt(h, K_PERMUTE, 0.0, 32.0 * bj * (double)m);
@@ -510,17 +529,34 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_CHECK(h, launch_reduce(part, 64, g.split_stride, ks, bj, (int)Nt, zbuf, 64, tblk, 64,
                                 bj, s));
     }
-    // 5. A_trailing -= Y Z (rows 0..bj-1 become R12)
+    // 5. A_trailing -= Y Z.  Rows 0..bj-1 (R12) are updated first on the main
+    // stream: the sample update and the next block's sample QRCP need only them.
+    // The other rows are updated on the side stream meanwhile; the next block
+    // waits for them before it permutes and factors its panel.
     {
-      KTimer kt(h, K_UPDATE, 2.0 * bj * (double)M * Nt,
-                8.0 * (2.0 * M * Nt + (double)M * bj + (double)bj * Nt));
-      RQ_CHECK(h, launch_update(Ctr, lda, (int)M, (int)Nt, ybuf, m, zbuf, 64, bj, s));
+      KTimer kt(h, K_UPDATE, 2.0 * bj * (double)bj * Nt,
+                8.0 * (2.0 * bj * Nt + (double)bj * bj + (double)bj * Nt));
+      RQ_CHECK(h, launch_update(Ctr, lda, bj, (int)Nt, ybuf, m, zbuf, 64, bj, s));
+    }
+    if (M > bj) {
+      RQ_CHECK(h, hipEventRecord(h->ev_z, s));
+      RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_z, 0));
+      {
+        const double Mr = (double)(M - bj);
+        KTimer kt(h, K_UPDATE, 2.0 * bj * Mr * Nt, 8.0 * (2.0 * Mr * Nt + Mr * bj + (double)bj * Nt),
+                  h->side);
+        RQ_CHECK(h, launch_update(Ctr + bj, lda, (int)(M - bj), (int)Nt, ybuf + bj, m, zbuf, 64, bj,
+                                  h->side));
+      }
+      RQ_CHECK(h, hipEventRecord(h->ev_u, h->side));
+      pending_rows = true;
     }
     // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
     if (col0 + bj < k)
       RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
                                mhat));
   }
+  if (pending_rows) RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
   return RQ_OK;
 }
 

@@ -11,12 +11,12 @@
 namespace rq {
 
 // ---------------------------------------------------------------------------
-// gemm_lx: each workgroup owns 64 output columns (16 per wave) and all P rows
-// (PB blocks of 16), over one K chunk.  The K index of MFMA step s in lane l is
+// gemm_lx for short K (at most 64 per chunk): each workgroup owns 64 output
+// columns (16 per wave) and all P rows (PB blocks of 16), over one K chunk.  The K index of MFMA step s in lane l is
 // k0 + 4 * (l / 16) + s, so each lane reads 4 consecutive rows of X per group of
 // 16 k values (both operands use the same ordering of k).
 template <int PB>
-__global__ __launch_bounds__(256) void gemm_lx_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) void gemm_lx_narrow_kernel(GemmArgs g) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + wave * 16 + (lane & 15);
@@ -72,16 +72,138 @@ __global__ __launch_bounds__(256) void gemm_lx_kernel(GemmArgs g) {
   }
 }
 
-void plan_split(int K, int N, int* ksplit, int* kchunk) {
-  const int tiles = (N + 63) / 64;
-  int ks = (1024 + tiles - 1) / tiles;             // aim for ~4 workgroups per CU
-  const int kmax = (K + 255) / 256;                // at least 256 rows per chunk
+// ---------------------------------------------------------------------------
+// gemm_lx: a workgroup owns 16 * NB output columns and all P rows (PB blocks of
+// 16) over one K chunk; its four waves take interleaved 16-row groups of the
+// chunk (wave w: groups w, w + 4, ...) and each holds the whole PB x NB block of
+// accumulators, so every loaded operand feeds PB or NB matrix-core products.
+// The K index of MFMA step s in lane l is k0 + 4 * (l / 16) + s: each lane reads
+// 4 consecutive rows of X (and of L when its k stride is 1) per group of 16 k.
+// The four waves' sums are combined in LDS in a fixed order, (w0 + w2) + (w1 + w3).
+template <int PB, int NB, bool LK1>
+__global__ __launch_bounds__(256, 2) void gemm_lx_kernel(GemmArgs g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int kq = lane >> 4;
+  const int kb = blockIdx.y * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  const double* xc[NB];
+  bool nok[NB];
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) {
+    const int n = blockIdx.x * 16 * NB + 16 * jb + l16;
+    nok[jb] = n < g.N;
+    xc[jb] = g.X + (nok[jb] ? (g.xcol ? g.xcol[n] : (int64_t)n) : 0) * g.ldx + 4 * kq;
+  }
+  // row 16 i + l16 of L (clamped: rows p >= P are never used), at k = 4 kq
+  const double* lr[PB];
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+    lr[i] = g.L + (int64_t)min(16 * i + l16, g.P - 1) * g.sLp + (int64_t)(4 * kq) * g.sLk;
+  dx4 acc[PB][NB];
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) acc[i][jb] = dx4{0.0, 0.0, 0.0, 0.0};
+
+#pragma unroll 1
+  for (int k0 = kb + 16 * wave; k0 < ke; k0 += 64) {
+    double la[PB][4], xb[NB][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool kok = k0 + 4 * kq + s < ke;
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) xb[jb][s] = (nok[jb] && kok) ? xc[jb][k0 + s] : 0.0;
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const bool ok = 16 * i + l16 < g.P && kok;
+        if (LK1)
+          la[i][s] = ok ? lr[i][k0 + s] : 0.0;
+        else
+          la[i][s] = ok ? lr[i][(int64_t)(k0 + s) * g.sLk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < PB; ++i)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) acc[i][jb] = mfma_f64(la[i][s], xb[jb][s], acc[i][jb]);
+  }
+  // ---- combine the four waves: (w0 + w2) + (w1 + w3) ---------------------------
+  constexpr int E = PB * NB * 4;
+  __shared__ double s_red[2][E][64];
+  if (wave >= 2) {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_red[wave - 2][(i * NB + jb) * 4 + v][lane] = acc[i][jb][v];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][jb][v] += s_red[wave][(i * NB + jb) * 4 + v][lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_red[0][(i * NB + jb) * 4 + v][lane] = acc[i][jb][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][jb][v] += s_red[0][(i * NB + jb) * 4 + v][lane];
+  // lane holds D[16 i + kq + 4 v][column 16 jb + l16]
+  double* o = g.out + (g.ksplit > 1 ? (int64_t)blockIdx.y * g.split_stride : 0);
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) {
+    if (!nok[jb]) continue;
+    const int64_t n = blockIdx.x * 16 * NB + 16 * jb + l16;
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * i + kq + 4 * v;
+        if (p >= g.P) continue;
+        if (g.ksplit > 1) {
+          o[p + n * g.ldout] = acc[i][jb][v];
+        } else {
+          double r = g.alpha * acc[i][jb][v];
+          if (g.beta != 0.0) r += g.beta * g.C[p + n * g.ldc];
+          o[p + n * g.ldout] = r;
+        }
+      }
+  }
+}
+
+// Output columns per workgroup of gemm_lx for P rows.
+static int lx_cols(int P) { return P <= 64 ? 64 : 32; }
+
+void plan_split(int K, int N, int* ksplit, int* kchunk, int P) {
+  const int tiles = (N + lx_cols(P) - 1) / lx_cols(P);
+  int ks = (512 + tiles - 1) / tiles;              // about two workgroups per CU
+  const int kmax = (K + 255) / 256;                // at least 64 rows per wave
   if (ks > kmax) ks = kmax;
   if (ks > 32) ks = 32;
   if (ks < 1) ks = 1;
   int kc = (K + ks - 1) / ks;
-  kc = ((kc + 15) / 16) * 16;
-  if (kc < 16) kc = 16;
+  kc = ((kc + 63) / 64) * 64;
+  if (kc < 64) kc = 64;
   ks = (K + kc - 1) / kc;
   if (ks < 1) ks = 1;
   *ksplit = ks;
@@ -90,15 +212,38 @@ void plan_split(int K, int N, int* ksplit, int* kchunk) {
 
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
   if (g.N <= 0 || g.P <= 0) return hipSuccess;
+  if (g.kchunk <= 0 || g.kchunk % 16 != 0) return hipErrorInvalidValue;
   const int pb = (g.P + 15) / 16;
-  dim3 grid((g.N + 63) / 64, g.ksplit);
+  if (g.kchunk <= 64) {
+    dim3 grid((g.N + 63) / 64, g.ksplit);
+    switch (pb) {
+      case 1: hipLaunchKernelGGL(gemm_lx_narrow_kernel<1>, grid, dim3(256), 0, s, g); break;
+      case 2: hipLaunchKernelGGL(gemm_lx_narrow_kernel<2>, grid, dim3(256), 0, s, g); break;
+      case 3: hipLaunchKernelGGL(gemm_lx_narrow_kernel<3>, grid, dim3(256), 0, s, g); break;
+      case 4: hipLaunchKernelGGL(gemm_lx_narrow_kernel<4>, grid, dim3(256), 0, s, g); break;
+      case 5: hipLaunchKernelGGL(gemm_lx_narrow_kernel<5>, grid, dim3(256), 0, s, g); break;
+      case 6: hipLaunchKernelGGL(gemm_lx_narrow_kernel<6>, grid, dim3(256), 0, s, g); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  dim3 grid((g.N + lx_cols(g.P) - 1) / lx_cols(g.P), g.ksplit);
+  const bool lk1 = g.sLk == 1;
+#define RQ_LX(pb_, nb_)                                                                  \
+  case pb_:                                                                              \
+    if (lk1)                                                                             \
+      hipLaunchKernelGGL((gemm_lx_kernel<pb_, nb_, true>), grid, dim3(256), 0, s, g);    \
+    else                                                                                 \
+      hipLaunchKernelGGL((gemm_lx_kernel<pb_, nb_, false>), grid, dim3(256), 0, s, g);   \
+    break;
   switch (pb) {
-    case 1: hipLaunchKernelGGL(gemm_lx_kernel<1>, grid, dim3(256), 0, s, g); break;
-    case 2: hipLaunchKernelGGL(gemm_lx_kernel<2>, grid, dim3(256), 0, s, g); break;
-    case 3: hipLaunchKernelGGL(gemm_lx_kernel<3>, grid, dim3(256), 0, s, g); break;
-    case 4: hipLaunchKernelGGL(gemm_lx_kernel<4>, grid, dim3(256), 0, s, g); break;
-    case 5: hipLaunchKernelGGL(gemm_lx_kernel<5>, grid, dim3(256), 0, s, g); break;
-    case 6: hipLaunchKernelGGL(gemm_lx_kernel<6>, grid, dim3(256), 0, s, g); break;
+    RQ_LX(1, 4)
+    RQ_LX(2, 4)
+    RQ_LX(3, 4)
+    RQ_LX(4, 4)
+    RQ_LX(5, 2)
+    RQ_LX(6, 2)
+#undef RQ_LX
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

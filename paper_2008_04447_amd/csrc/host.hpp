@@ -59,6 +59,9 @@ struct rq_handle_s {
   size_t ws_bytes = 0;
   int64_t* status = nullptr;   // device int64[4]
   uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag
+  int max_groups = 128;        // workgroups one persistent sample-QRCP launch may use
+  hipStream_t side = nullptr;  // second stream of the RQRCP block loop (created on first use)
+  hipEvent_t ev_z = nullptr, ev_u = nullptr;
   std::string last_error;
   bool prof = false;
   std::vector<rq::ProfRec> recs;
@@ -119,8 +122,10 @@ struct KTimer {
   rq_handle h;
   int cls;
   double f, b;
+  hipStream_t s;
   hipEvent_t e0 = nullptr;
-  KTimer(rq_handle h_, int cls_, double f_, double b_);
+  KTimer(rq_handle h_, int cls_, double f_, double b_) : KTimer(h_, cls_, f_, b_, h_->stream) {}
+  KTimer(rq_handle h_, int cls_, double f_, double b_, hipStream_t s_);
   ~KTimer();
 };
 

@@ -21,7 +21,10 @@ struct SqArgs {
 };
 int sq_lm(int ell);    // padded register height used for a given ell (0 = unsupported)
 int sq_record_stride(int lm);
-int sq_columns_per_group();   // sample columns held by one workgroup
+// Workgroups of the sample QRCP kernel for N columns: 128 columns per workgroup
+// (8 lanes each) when that needs at most max_groups, else 256 (4 lanes each).
+int sq_groups(int64_t N, int max_groups);
+int sq_max_groups(int64_t N);   // upper bound of sq_groups over max_groups (record sizing)
 hipError_t launch_sample_qrcp(const SqArgs& a, int lm, hipStream_t s);
 
 // ---- panel Householder QR + compact-WY T (persistent) ----------------------
@@ -54,7 +57,8 @@ struct GemmArgs {
   const int64_t* xcol = nullptr;       // optional: column n of X is X + xcol[n] * ldx
 };
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
-void plan_split(int K, int N, int* ksplit, int* kchunk);
+// split-K plan of launch_gemm_lx for P output rows (kchunk a multiple of 64)
+void plan_split(int K, int N, int* ksplit, int* kchunk, int P = 64);
 
 // ---- BF16 MFMA contractions (FP32 accumulate, FP64 results) -----------------
 struct GemmArgsF {

@@ -1,8 +1,9 @@
 // Partial QRCP of the (b+p) x N sample (the pivot block of Algorithms 3-5).
 //
-// Each sample column is held in registers by a quad of 4 lanes for the whole
-// kernel (lane q of the quad keeps rows q, q+4, q+8, ...; ell <= 96, padded
-// with zero rows), 256 columns per 1024-thread workgroup.  A pivot step needs
+// Each sample column is held in registers by a group of Q lanes (8, or 4 for
+// very wide samples) for the whole kernel: lane q of the group keeps rows q,
+// q+Q, q+2Q, ... (ell <= 96, padded with zero rows), 1024 / Q columns per
+// 1024-thread workgroup.  A pivot step needs
 // the column of largest trailing 2-norm over all workgroups, so every step ends
 // with one cross-workgroup exchange: each workgroup publishes its best
 // (norm^2, position) and that column's values; after the barrier every
@@ -16,13 +17,21 @@
 namespace rq {
 
 constexpr int kSqThreads = 1024;
-constexpr int kQ = 4;                          // lanes per column
-constexpr int kSqCols = kSqThreads / kQ;       // columns per workgroup
 constexpr int kSqWaves = kSqThreads / 64;
 constexpr int kSpecCap = 8192;                 // doubles of LDS for the one-round candidate fetch
 
-template <int LM>
+// Sum over the Q lanes holding one column.
+template <int Q>
+RQ_DEV double column_sum(double v) {
+  v = quad_sum(v);
+  if (Q == 8) v += dpp_f64<kDppHalfMirror>(v);
+  return v;
+}
+
+template <int LM, int Q>
 __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
+  constexpr int kQ = Q;                        // lanes per column
+  constexpr int kSqCols = kSqThreads / kQ;     // columns per workgroup
   constexpr int RPL = LM / kQ;                 // rows per lane
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -37,6 +46,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   __shared__ double s_wv[kSqWaves];
   __shared__ int s_wp[kSqWaves], s_ww[kSqWaves];
   __shared__ double s_all[kSpecCap];
+  __shared__ double s_v[kSqWaves][LM];         // each wave's copy of the reflector
 
   double x[RPL];
 #pragma unroll
@@ -54,7 +64,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       else
         s0 += x[i] * x[i];
     }
-    nu2 = quad_sum(s0 + s1);
+    nu2 = column_sum<kQ>(s0 + s1);
   }
   int pos = own ? c : INT_MAX;
   bool active = own;
@@ -171,19 +181,24 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
     }
     // ---- apply the reflection to the remaining columns ---------------------------
+    // Each wave writes the reflector once into its own LDS row and reads it back
+    // (LDS operations of one wave complete in order; no workgroup barrier).
+    for (int r = lane; r < LM; r += 64) s_v[wave][r] = (r < j) ? 0.0 : (r == j ? 1.0 : col[r] * scale);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (active) {
       double v[RPL];
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const int r = q + kQ * i;
-        v[i] = (r < j) ? 0.0 : (r == j ? 1.0 : col[r] * scale);
+        v[i] = s_v[wave][q + kQ * i];
         if (i & 1)
           d1 += v[i] * x[i];
         else
           d0 += v[i] * x[i];
       }
-      const double d = tau * quad_sum(d0 + d1);
+      const double d = tau * column_sum<kQ>(d0 + d1);
       double n0 = 0.0, n1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
@@ -194,7 +209,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
         else
           n0 += sq;
       }
-      nu2 = quad_sum(n0 + n1);
+      nu2 = column_sum<kQ>(n0 + n1);
     }
     __syncthreads();   // s_all and the wave winners are rewritten in the next step
   }
@@ -221,11 +236,25 @@ int sq_lm(int ell) {
 
 int sq_record_stride(int lm) { return ((lm + 2 + 7) / 8) * 8; }
 
-int sq_columns_per_group() { return kSqCols; }
+// Every workgroup of the persistent kernel must be resident at once, so the
+// wider layout (8 lanes per column, twice the workgroups) is used only within
+// the caller's workgroup allowance.
+int sq_groups(int64_t N, int max_groups) {
+  const int64_t g8 = (N + 127) / 128;
+  return (int)(g8 <= max_groups ? g8 : (N + 255) / 256);
+}
+
+int sq_max_groups(int64_t N) { return (int)((N + 127) / 128); }
 
 template <int LM>
 static hipError_t launch_lm(const SqArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(sample_qrcp_kernel<LM>, dim3(a.nwg), dim3(kSqThreads), 0, s, a);
+  // the layout follows from the workgroup count chosen by sq_groups
+  const bool wide = (int64_t)a.nwg * 128 >= a.N;
+  if (a.nwg < 1 || (int64_t)a.nwg * 256 < a.N) return hipErrorInvalidValue;
+  if (wide)
+    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 8>), dim3(a.nwg), dim3(kSqThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4>), dim3(a.nwg), dim3(kSqThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -198,8 +198,9 @@ rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t
   if (max_ell < 1 || max_ell > RQ_MAX_ELL) return -7;
   if (!out) return -8;
   // persistent kernels of all slots must be able to be resident together
-  const int64_t groups = (std::max(max_m, max_n) + 255) / 256;
-  if ((int64_t)slots * groups > 192) return RQ_E_UNSUPPORTED;
+  const int cap = 192 / slots;
+  if (sq_groups(max_n, cap) > cap || (std::max(max_m, max_n) + kPanelRows - 1) / kPanelRows > cap)
+    return RQ_E_UNSUPPORTED;
   DeviceGuard guard(device);
   rq_server s = new rq_server_s();
   s->device = device;
@@ -223,6 +224,7 @@ rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t
     rq_handle h = nullptr;
     st = rq_create(&h, device, str);
     if (st != RQ_OK) break;
+    h->max_groups = cap;
     s->handles.push_back(h);
     st = reserve(h, ws);
   }
