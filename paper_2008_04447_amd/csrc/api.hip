@@ -159,7 +159,7 @@ rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* 
 
 size_t sq_rec_doubles(int ell, int64_t N) {
   const int lm = sq_lm(ell);
-  return (size_t)2 * sq_max_groups(N) * sq_record_stride(lm);
+  return (size_t)RQ_MAX_B * sq_max_groups(N) * sq_record_stride(lm);   // one slot per step
 }
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
@@ -180,7 +180,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.src_top = w.src_top;
   a.dst_low = w.dst_low;
   a.perm = perm;
-  RQ_CHECK(h, launch_zero_u32(h->sync, 2, h->stream));
+  RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
   KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
   RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
   return RQ_OK;
@@ -188,7 +188,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
 
 static int panel_groups(int64_t M) { return (int)((M + kPanelRows - 1) / kPanelRows); }
 
-size_t panel_rec_doubles(int64_t M) { return (size_t)2 * panel_groups(M) * 3 * 64; }
+size_t panel_rec_doubles(int64_t M) { return (size_t)(RQ_MAX_B + 1) * panel_groups(M) * 3 * 64; }
 
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt) {
@@ -207,7 +207,7 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
   a.ldy = ldy;
   a.T = T;
   a.ldt = ldt;
-  RQ_CHECK(h, launch_zero_u32(h->sync, 2, h->stream));
+  RQ_CHECK(h, launch_exchange_prep(h->sync, rec, (int64_t)(bj + 1) * a.nwg * 3 * 64, h->stream));
   KTimer kt(h, K_PANEL, 2.0 * (double)M * bj * bj, 8.0 * (double)M * (2.0 * bj + 64));
   RQ_CHECK(h, launch_panel(a, h->stream));
   return RQ_OK;

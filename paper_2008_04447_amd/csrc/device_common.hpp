@@ -63,6 +63,45 @@ RQ_DEV bool grid_barrier(uint32_t* counter, uint32_t* abort_flag, uint32_t nwg, 
   return s_ok != 0;
 }
 
+// ---- published records (persistent-kernel exchange without a barrier) -------
+// Each workgroup publishes its per-step record into a slot of its own for that
+// step, which holds a sentinel until then (written by a kernel that ran
+// before), and readers wait on the record words themselves: one round trip
+// through device-coherent memory both synchronizes and delivers the data, and
+// as no slot is reused within a launch, no fence or reset is needed.  The
+// sentinel is a signalling-NaN bit pattern, which arithmetic never produces
+// (it quiets NaNs); kernels canonicalize NaNs they copy from inputs.
+constexpr unsigned long long kUnpublished = 0x7FF4DEADBEEF0001ull;
+
+RQ_DEV void publish(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+RQ_DEV unsigned long long peek(const double* p) {
+  return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+RQ_DEV double canonical(double v) { return (v != v) ? __builtin_nan("") : v; }
+
+// One bounded wait iteration: false (and the abort flag set) once the wait has
+// lasted kSpinLimit polls or another workgroup aborted (checked every 64 polls,
+// so the common short wait costs no extra round trip).
+RQ_DEV bool keep_waiting(uint32_t& it, uint32_t* abort_flag, int64_t* status) {
+  if ((it & 63u) == 63u &&
+      __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    return false;
+  if (++it > kSpinLimit) {
+    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    raise_status(status, kErrTimeout);
+    return false;
+  }
+  __builtin_amdgcn_s_sleep(1);
+  return true;
+}
+
 // True when an earlier kernel of this handle already timed out: persistent
 // kernels then leave at once instead of waiting again.
 RQ_DEV bool prior_timeout(const int64_t* status) {

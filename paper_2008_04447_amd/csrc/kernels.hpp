@@ -10,7 +10,7 @@ struct SqArgs {
   double* B;           // ell x N sample, column-major, leading dimension ldb
   int64_t ldb;
   int ell, N, steps, nwg;
-  double* rec;         // exchange records [2][nwg][rs]
+  double* rec;         // exchange records [steps][nwg][rs], unpublished at launch
   int rs;
   uint32_t* counter;   // zeroed before launch
   uint32_t* abort_flag;
@@ -32,7 +32,7 @@ struct PanelArgs {
   double* A;           // top-left of the M x bj panel, leading dimension lda
   int64_t lda;
   int M, bj, nwg;
-  double* rec;         // [2][nwg][3 * 64]
+  double* rec;         // exchange records [bj + 1][nwg][3 * 64], unpublished at launch
   uint32_t* counter;
   uint32_t* abort_flag;
   int64_t* status;
@@ -124,6 +124,9 @@ hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, const int* s
 
 hipError_t launch_iota(int64_t* v, int n, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s);
+// Clears the barrier counter and abort flag (sync[0..1]) and marks the n record
+// words of a persistent kernel's exchange as unpublished.
+hipError_t launch_exchange_prep(uint32_t* sync, double* rec, int64_t n, hipStream_t s);
 hipError_t launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,
                          int cols, hipStream_t s);
 

@@ -13,8 +13,9 @@
 // and applies the reflection locally, so one exchange per column suffices.
 // The same exchange also carries Y(:, c)^T y_{j-1} for the forward recurrence
 // T[:j-1, j-1] = -tau_{j-1} T[:j-1, :j-1] (Y^T y_{j-1}); one extra exchange at
-// the end finishes the last column of T.  All sums over workgroups are taken in
-// one fixed order, so every workgroup derives bitwise the same reflector.
+// the end finishes the last column of T.  The partial sums travel as published
+// records (device_common.hpp); all sums over workgroups are taken in one fixed
+// order, so every workgroup derives bitwise the same reflector.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -24,6 +25,8 @@ constexpr int kPanelThreads = 1024;
 constexpr int kPC = 64;                                  // max panel columns
 constexpr int kPG = kPanelThreads / kPC;                 // row groups (16 lanes of a wave)
 constexpr int kPR = kPanelRows / kPG;                    // rows per thread (16)
+constexpr int kRC = 32;                                  // records per combine chunk
+constexpr int kPollP = (2 * kRC * kPC + kPC + kPanelThreads - 1) / kPanelThreads;   // words per thread
 
 __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   const int t = threadIdx.x;
@@ -37,13 +40,14 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
 
   __shared__ double s_bc[2][kPanelRows];   // column j (before its reflection), by step parity
   __shared__ double s_p[kPC];
+  __shared__ double s_words[2 * kRC * kPC + kPC];   // one chunk of record words
   __shared__ double s_T[kPC][kPC + 1];
 
   double x[kPR];
 #pragma unroll
   for (int i = 0; i < kPR; ++i) {
     const int r = rbase + g + kPG * i;
-    x[i] = (colok && r < a.M) ? a.A[r + (int64_t)c * a.lda] : 0.0;
+    x[i] = (colok && r < a.M) ? canonical(a.A[r + (int64_t)c * a.lda]) : 0.0;
   }
   if (wg == 0) {
     for (int e = t; e < kPC * (kPC + 1); e += kPanelThreads) (&s_T[0][0])[e] = 0.0;
@@ -82,29 +86,78 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
     pg = row16_sum(pg);
     pt = row16_sum(pt);
     pp = row16_sum(pp);
-    double* rec = a.rec + ((int64_t)buf * a.nwg + wg) * (3 * kPC);
+    double* rec = a.rec + ((int64_t)j * a.nwg + wg) * (3 * kPC);
     if (g == 0) {
-      rec[c] = pg;
-      rec[kPC + c] = pt;
-      rec[2 * kPC + c] = pp;
+      publish(rec + c, pg);
+      publish(rec + kPC + c, pt);
+      publish(rec + 2 * kPC + c, pp);
     }
-    if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, (uint32_t)j, a.status)) return;
-    // ---- combine over workgroups: lane g sums workgroups g, g + 16, ..., then
-    // the 16 lanes are summed; every wave also forms column j's sums itself ------
-    const double* rj = a.rec + (int64_t)buf * a.nwg * (3 * kPC);
+    // ---- combine over workgroups --------------------------------------------
+    // The Gram words of every record (and, in workgroup 0, the T words) are
+    // waited for with coalesced loads into LDS, kRC records at a time; then lane
+    // g sums records g, g + 16, ... in increasing order, and the 16 lanes are
+    // summed.  Every wave also forms column j's sums itself.
+    const double* rj = a.rec + (int64_t)j * a.nwg * (3 * kPC);
     const int jj = j < bj ? j : 0;
-    double sg = 0.0, sgj = 0.0, sp = 0.0;
-    for (int w = g; w < a.nwg; w += kPG) {
-      const double* rw = rj + (int64_t)w * 3 * kPC;
-      sg += rw[c];
-      sgj += rw[jj];
-      if (wg == 0) sp += rw[2 * kPC + c];
+    const bool need_p = wg == 0;
+    double sg = 0.0, sgj = 0.0, sp = 0.0, topc = 0.0, alpha = 0.0;
+    bool ok = true;
+    for (int wb = 0; wb < a.nwg; wb += kRC) {
+      const int nrec = min(kRC, a.nwg - wb);
+      const int ng = nrec * kPC;                         // Gram words of this chunk
+      const int np = need_p ? ng : 0;                    // T words (workgroup 0)
+      const int ntop = wb == 0 ? kPC : 0;                // row-j words of workgroup 0
+      const int total = ng + np + ntop;
+      // word e: [0, ng) Gram, [ng, ng + np) T, then the row-j words
+      auto addr = [&](int e) -> const double* {
+        if (e < ng) return rj + (int64_t)(wb + e / kPC) * 3 * kPC + (e % kPC);
+        if (e < ng + np) {
+          const int f = e - ng;
+          return rj + (int64_t)(wb + f / kPC) * 3 * kPC + 2 * kPC + (f % kPC);
+        }
+        return rj + kPC + (e - ng - np);
+      };
+      unsigned long long bw[kPollP];
+#pragma unroll
+      for (int k = 0; k < kPollP; ++k) {
+        const int e = t + k * kPanelThreads;
+        bw[k] = (e < total) ? peek(addr(e)) : 0ull;
+      }
+      uint32_t it = 0;
+      while (ok) {
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < kPollP; ++k) all = all && bw[k] != kUnpublished;
+        if (all) break;
+        if (!keep_waiting(it, a.abort_flag, a.status)) {
+          ok = false;
+          break;
+        }
+#pragma unroll
+        for (int k = 0; k < kPollP; ++k) {
+          const int e = t + k * kPanelThreads;
+          if (e < total && bw[k] == kUnpublished) bw[k] = peek(addr(e));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kPollP; ++k) {
+        const int e = t + k * kPanelThreads;
+        if (e < total) s_words[e] = __longlong_as_double((long long)bw[k]);
+      }
+      if (__syncthreads_or(!ok)) return;
+      for (int w = g; w < nrec; w += kPG) {
+        sg += s_words[w * kPC + c];
+        sgj += s_words[w * kPC + jj];
+        if (need_p) sp += s_words[ng + w * kPC + c];
+      }
+      if (wb == 0) {
+        topc = s_words[ng + np + c];
+        alpha = s_words[ng + np + jj];
+      }
+      __syncthreads();                                   // s_words is refilled by the next chunk
     }
     sg = row16_sum(sg);
     sgj = row16_sum(sgj);
-    // row j of the panel lies in workgroup 0 (j < 64 < 256 rows per workgroup)
-    const double topc = rj[kPC + c];
-    const double alpha = rj[kPC + jj];
     // ---- T column j-1 (workgroup 0): 16 lanes per row of T --------------------
     if (wg == 0 && j >= 1) {
       const int jc = j - 1;

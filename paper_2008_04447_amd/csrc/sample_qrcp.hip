@@ -6,8 +6,9 @@
 // 1024-thread workgroup.  A pivot step needs
 // the column of largest trailing 2-norm over all workgroups, so every step ends
 // with one cross-workgroup exchange: each workgroup publishes its best
-// (norm^2, position) and that column's values; after the barrier every
-// workgroup picks the same winner, forms the same Householder vector from the
+// (norm^2, position) and that column's values as a record (see the published
+// records in device_common.hpp); once all records are in, every workgroup
+// picks the same winner, forms the same Householder vector from the
 // published column and applies it to its own columns.  Norms of rows j+1.. are
 // recomputed from the transformed columns (no downdating).  Ties go to the
 // lowest current position; positions follow the transpositions j <-> p_j.
@@ -19,6 +20,7 @@ namespace rq {
 constexpr int kSqThreads = 1024;
 constexpr int kSqWaves = kSqThreads / 64;
 constexpr int kSpecCap = 8192;                 // doubles of LDS for the one-round candidate fetch
+constexpr int kPoll = kSpecCap / kSqThreads;   // record words polled per thread
 
 // Sum over the Q lanes holding one column.
 template <int Q>
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int r = q + kQ * i;
-    x[i] = (own && r < a.ell) ? a.B[r + (int64_t)c * a.ldb] : 0.0;
+    x[i] = (own && r < a.ell) ? canonical(a.B[r + (int64_t)c * a.ldb]) : 0.0;
   }
   double nu2;
   {
@@ -94,36 +96,57 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       int w = (lane < kSqWaves) ? s_ww[lane] : 0;
       wave_argmax(v, p, w);
       const int owner = (p == INT_MAX) ? -1 : w;
-      double* rec = a.rec + ((int64_t)(j & 1) * a.nwg + wg) * a.rs;
+      double* rec = a.rec + ((int64_t)j * a.nwg + wg) * a.rs;
       if (cl == owner) {
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) rec[2 + q + kQ * i] = x[i];
+        for (int i = 0; i < RPL; ++i) publish(rec + 2 + q + kQ * i, x[i]);
       }
-      if (owner < 0 && t < LM) rec[2 + t] = 0.0;
+      if (owner < 0 && t < LM) publish(rec + 2 + t, 0.0);
       if (t == 0) {
-        rec[0] = v;
-        rec[1] = (double)p;
+        publish(rec, v);
+        publish(rec + 1, (double)p);
       }
     }
-    // ---- exchange ----------------------------------------------------------
-    if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, (uint32_t)j, a.status)) return;
-    const double* rj = a.rec + (int64_t)(j & 1) * a.nwg * a.rs;
+    // ---- exchange: wait for every workgroup's record of this step -------------
+    const double* rj = a.rec + (int64_t)j * a.nwg * a.rs;
     // all candidates (value, position) and, when they fit in LDS, their columns,
-    // fetched in one round of independent loads
+    // each thread polling up to kPoll words at once
     const bool spec = a.nwg * (LM + 2) <= kSpecCap;
     const int per = spec ? LM + 2 : 2;
-    if (spec) {
-      for (int e = t; e < a.nwg * per; e += kSqThreads) {
+    bool ok = true;
+    {
+      const int total = a.nwg * per;
+      unsigned long long b[kPoll];
+#pragma unroll
+      for (int k = 0; k < kPoll; ++k) {
+        const int e = t + k * kSqThreads;
         const int w = e / per, f = e - w * per;
-        s_all[e] = rj[(int64_t)w * a.rs + f];
+        b[k] = (e < total) ? peek(rj + (int64_t)w * a.rs + f) : 0ull;
       }
-    } else {
-      for (int w = t; w < a.nwg; w += kSqThreads) {
-        s_all[2 * w] = rj[(int64_t)w * a.rs];
-        s_all[2 * w + 1] = rj[(int64_t)w * a.rs + 1];
+      uint32_t it = 0;
+      while (true) {
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < kPoll; ++k) all = all && b[k] != kUnpublished;
+        if (all) break;
+        if (!keep_waiting(it, a.abort_flag, a.status)) {
+          ok = false;
+          break;
+        }
+#pragma unroll
+        for (int k = 0; k < kPoll; ++k) {
+          const int e = t + k * kSqThreads;
+          const int w = e / per, f = e - w * per;
+          if (e < total && b[k] == kUnpublished) b[k] = peek(rj + (int64_t)w * a.rs + f);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kPoll; ++k) {
+        const int e = t + k * kSqThreads;
+        if (e < total) s_all[e] = __longlong_as_double((long long)b[k]);
       }
     }
-    __syncthreads();
+    if (__syncthreads_or(!ok)) return;
     // every wave finds the same winner and forms the same reflector
     int wwg = 0, wpos;
     {
@@ -149,8 +172,20 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
     if (!spec) {
       // columns did not fit: fetch the winner's column into the front of s_all
       __syncthreads();
-      if (t < LM) s_all[2 + t] = rj[(int64_t)wwg * a.rs + 2 + t];
-      __syncthreads();
+      if (t < LM) {
+        const double* src = rj + (int64_t)wwg * a.rs + 2 + t;
+        unsigned long long bt = peek(src);
+        uint32_t it = 0;
+        while (bt == kUnpublished) {
+          if (!keep_waiting(it, a.abort_flag, a.status)) {
+            ok = false;
+            break;
+          }
+          bt = peek(src);
+        }
+        s_all[2 + t] = __longlong_as_double((long long)bt);
+      }
+      if (__syncthreads_or(!ok)) return;
       wwg = 0;
     }
     const double* col = s_all + (spec ? wwg * (LM + 2) : 0) + 2;   // winner's column in LDS
