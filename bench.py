@@ -52,7 +52,40 @@ def profile_table(h):
     return out
 
 
-def roofline(prof, steps):
+PROFILE = os.path.join(ROOT, "profiles", "rqrcp_fp64_8000_kernels.txt")
+KERNEL_SOURCES = {"sample_qrcp": ["sample_qrcp.hip"], "panel": ["panel.hip"],
+                  "inner_products": ["blas.hip"], "trailing_update": ["blas.hip"]}
+
+
+def source_hash(cls):
+    """Hash of the sources a kernel class is built from (as recorded in the profile)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2008_04447_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES[cls] + ["device_common.hpp", "kernels.hpp"]:
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed
+    rocprofv3 summary, or None when absent or measured on other kernel sources."""
+    if cls not in KERNEL_SOURCES or not os.path.exists(PROFILE):
+        return None
+    with open(PROFILE) as f:
+        for line in f:
+            if not line.startswith("TRAFFIC "):
+                continue
+            kv = dict(item.split("=", 1) for item in line.split()[1:])
+            if kv.get("workload") == workload and kv.get("class") == cls:
+                if kv.get("source") != source_hash(cls):
+                    return None
+                return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
+def roofline(prof, steps, workload=None):
     """Roofline entry of the kernel class with the largest total time."""
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     sec = rec["ms"] * 1e-3
@@ -65,7 +98,8 @@ def roofline(prof, steps):
         peak = PEAK["hbm_gbs"]
         bound, unit = "hbm", "GB/s"
     return {"kernel": name, "bound": bound, "achieved": round(achieved, 4), "peak": peak,
-            "unit": unit, "frac": round(achieved / peak, 5), "traffic": None,
+            "unit": unit, "frac": round(achieved / peak, 5),
+            "traffic": measured_traffic(workload, name) if workload else None,
             "launches_per_step": rec["launches"] / steps,
             "avg_launch_us": round(rec["ms"] * 1e3 / rec["launches"], 3),
             "share_of_step": None}
@@ -165,7 +199,7 @@ def bench_rqrcp(args):
         log(f"plain QRCP {qms:.2f} ms/step -> RQRCP speedup {qms / ms:.2f}x")
         del qcopies
 
-    roof = roofline(prof, args.steps)
+    roof = roofline(prof, args.steps, f"rqrcp_fp64_{m}x{n}_gauss")
     roof["share_of_step"] = round(prof[roof["kernel"]]["ms"] / args.steps / ms, 4)
     res = {
         "metric": "RQRCP FP64 TFLOP/s (nominal 4n^3/3) on one MI355X",

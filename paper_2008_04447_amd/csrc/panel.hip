@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   if (prior_timeout(a.status)) return;
 
   __shared__ double s_bc[2][kPanelRows];   // column j (before its reflection), by step parity
-  __shared__ double s_p[kPC];
+  __shared__ double s_S[kPC][kPC + 1];     // workgroup 0: S[q][i] = y_q^T y_i for q < i
+  __shared__ double s_tau[kPC];
   __shared__ double s_words[2 * kRC * kPC + kPC];   // one chunk of record words
   __shared__ double s_T[kPC][kPC + 1];
 
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   if (wg == 0) {
     for (int e = t; e < kPC * (kPC + 1); e += kPanelThreads) (&s_T[0][0])[e] = 0.0;
   }
-  double prev_scale = 0.0, prev_tau = 0.0;
+  double prev_scale = 0.0;
 
   for (int j = 0; j <= bj; ++j) {
     const int buf = j & 1;
@@ -158,25 +159,10 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
     }
     sg = row16_sum(sg);
     sgj = row16_sum(sgj);
-    // ---- T column j-1 (workgroup 0): 16 lanes per row of T --------------------
+    // ---- column j-1 of S = Y^T Y (workgroup 0); T is formed after the loop ----
     if (wg == 0 && j >= 1) {
-      const int jc = j - 1;
       sp = row16_sum(sp);
-      if (g == 0) s_p[c] = sp;
-      __syncthreads();
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < kPC / kPG; ++k) {
-        const int q = g + kPG * k;
-        acc += (q >= c && q < jc) ? s_T[c][q] * s_p[q] : 0.0;
-      }
-      acc = row16_sum(acc);
-      if (g == 0) {
-        if (c < jc)
-          s_T[c][jc] = -prev_tau * acc;
-        else if (c == jc)
-          s_T[jc][jc] = prev_tau;
-      }
+      if (g == 0) s_S[c][j - 1] = sp;
     }
     if (j == bj) break;
     // ---- reflector j and its application -------------------------------------
@@ -206,11 +192,33 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
         x[i] = (r > j) ? x[i] * scale : (r == j ? beta : x[i]);
       }
     }
-    if (wg == 0 && t == 0) a.tau[j] = tau;
+    if (wg == 0 && t == 0) {
+      a.tau[j] = tau;
+      s_tau[j] = tau;
+    }
     prev_scale = scale;
-    prev_tau = tau;
   }
   __syncthreads();
+  // ---- T by the forward recurrence T[:i, i] = -tau_i T[:i, :i] S[:i, i],
+  // T[i, i] = tau_i (workgroup 0; 16 lanes per row of T) ----------------------
+  if (wg == 0) {
+    for (int i = 0; i < bj; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kPC / kPG; ++k) {
+        const int q = g + kPG * k;
+        acc += (q >= c && q < i) ? s_T[c][q] * s_S[q][i] : 0.0;
+      }
+      acc = row16_sum(acc);
+      if (g == 0) {
+        if (c < i)
+          s_T[c][i] = -s_tau[i] * acc;
+        else if (c == i)
+          s_T[i][i] = s_tau[i];
+      }
+      __syncthreads();
+    }
+  }
   // ---- write back: R / reflector tails into the panel, explicit Y, T --------
 #pragma unroll
   for (int i = 0; i < kPR; ++i) {
