@@ -188,7 +188,9 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
 
 static int panel_groups(int64_t M) { return (int)((M + kPanelRows - 1) / kPanelRows); }
 
-size_t panel_rec_doubles(int64_t M) { return (size_t)(RQ_MAX_B + 1) * panel_groups(M) * 3 * 64; }
+size_t panel_rec_doubles(int64_t M) {
+  return (size_t)(RQ_MAX_B + 1) * panel_groups(M) * 3 * 64 + (size_t)panel_cholqr_doubles(panel_groups(M));
+}
 
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt) {
@@ -207,7 +209,12 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
   a.ldy = ldy;
   a.T = T;
   a.ldt = ldt;
-  RQ_CHECK(h, launch_exchange_prep(h->sync, rec, (int64_t)(bj + 1) * a.nwg * 3 * 64, h->stream));
+  // the Cholesky-QR route is tried for panels of two or more columns
+  const int64_t hh = (int64_t)(bj + 1) * a.nwg * 3 * 64;
+  a.crec = bj >= 2 ? rec + hh : nullptr;
+  a.fallback = a.crec ? h->sync + 2 : nullptr;
+  RQ_CHECK(h, launch_exchange_prep(h->sync, rec, hh + (a.crec ? panel_cholqr_doubles(a.nwg) : 0),
+                                   h->stream));
   KTimer kt(h, K_PANEL, 2.0 * (double)M * bj * bj, 8.0 * (double)M * (2.0 * bj + 64));
   RQ_CHECK(h, launch_panel(a, h->stream));
   return RQ_OK;

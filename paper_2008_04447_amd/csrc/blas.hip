@@ -501,11 +501,11 @@ hipError_t launch_iota(int64_t* v, int n, hipStream_t s) {
 
 __global__ void exchange_prep_kernel(uint32_t* sync, unsigned long long* rec, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < 2) sync[e] = 0u;
+  if (e < 3) sync[e] = 0u;
   if (e < n) rec[e] = kUnpublished;
 }
 hipError_t launch_exchange_prep(uint32_t* sync, double* rec, int64_t n, hipStream_t s) {
-  const int64_t total = n > 2 ? n : 2;
+  const int64_t total = n > 3 ? n : 3;
   hipLaunchKernelGGL(exchange_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      sync, reinterpret_cast<unsigned long long*>(rec), n);
   return hipGetLastError();

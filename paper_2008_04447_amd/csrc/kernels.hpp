@@ -33,6 +33,8 @@ struct PanelArgs {
   int64_t lda;
   int M, bj, nwg;
   double* rec;         // exchange records [bj + 1][nwg][3 * 64], unpublished at launch
+  double* crec;        // null, or the records of the Cholesky-QR route (panel_cholqr_doubles)
+  uint32_t* fallback;  // with crec: zero at launch, set when the column-by-column route must run
   uint32_t* counter;
   uint32_t* abort_flag;
   int64_t* status;
@@ -43,6 +45,8 @@ struct PanelArgs {
   int64_t ldt;
 };
 constexpr int kPanelRows = 256;   // rows held by one workgroup
+// record words of the Cholesky-QR route of the panel for nwg workgroups
+inline int64_t panel_cholqr_doubles(int nwg) { return (int64_t)2 * nwg * 4096 + 2 * 4096 + 4096 + 64; }
 hipError_t launch_panel(const PanelArgs& a, hipStream_t s);
 
 // ---- FP64 MFMA contraction D(P x N) = L(P x K) X(K x N) --------------------
@@ -124,7 +128,7 @@ hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, const int* s
 
 hipError_t launch_iota(int64_t* v, int n, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s);
-// Clears the barrier counter and abort flag (sync[0..1]) and marks the n record
+// Clears the barrier counter, abort flag and panel fallback flag (sync[0..2]) and marks the n record
 // words of a persistent kernel's exchange as unpublished.
 hipError_t launch_exchange_prep(uint32_t* sync, double* rec, int64_t n, hipStream_t s);
 hipError_t launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,

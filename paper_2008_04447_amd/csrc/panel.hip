@@ -16,6 +16,20 @@
 // the end finishes the last column of T.  The partial sums travel as published
 // records (device_common.hpp); all sums over workgroups are taken in one fixed
 // order, so every workgroup derives bitwise the same reflector.
+//
+// Well-conditioned panels take a shorter route with a handful of exchanges per
+// panel instead of one per column: two passes of Cholesky QR (Gram matrix
+// G = X^T X reduced over workgroups, G = R^T R, X <- X R^{-1}; the second pass
+// restores orthogonality) give Q and R, and the Householder vectors with the
+// same sign convention as the column-by-column QR are then reconstructed from
+// Q by an LU factorization without pivoting of Q11 - S, S = diag(+-1) chosen
+// at each step against the pivot's sign: Y = (Q - [S; 0]) U^{-1} with
+// Y11 = L11, T = -U S L11^{-T}, and the triangular factor is S R.  This is the
+// same reflector set the Householder QR produces, up to rounding.  The route is
+// taken only when the first Cholesky factor has positive pivots whose largest
+// to smallest ratio is at most kCondMax; otherwise every workgroup reaches the
+// same decision and falls back to the column-by-column loop, with the panel
+// still untouched in registers.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -27,6 +41,380 @@ constexpr int kPG = kPanelThreads / kPC;                 // row groups (16 lanes
 constexpr int kPR = kPanelRows / kPG;                    // rows per thread (16)
 constexpr int kRC = 32;                                  // records per combine chunk
 constexpr int kPollP = (2 * kRC * kPC + kPC + kPanelThreads - 1) / kPanelThreads;   // words per thread
+constexpr int kLd = kPC + 1;                             // row stride of 64 x 64 matrices in LDS
+constexpr int kRegion = 4416;                            // doubles per LDS region
+constexpr int kWords = kPC * kPC;                        // one 64 x 64 matrix as record words
+constexpr double kCondMax = 16384.0;
+
+// Waits for `total` record words (at most MAXW per thread): word e comes from
+// src(e) and is handed to put(e, value).  False on timeout/abort.
+template <int MAXW, class Src, class Put>
+RQ_DEV bool wait_words(Src src, int total, Put put, int t, uint32_t* abort_flag,
+                       int64_t* status) {
+  unsigned long long b[MAXW];
+#pragma unroll
+  for (int k = 0; k < MAXW; ++k) {
+    const int e = t + k * kPanelThreads;
+    b[k] = (e < total) ? peek(src(e)) : 0ull;
+  }
+  uint32_t it = 0;
+  bool ok = true;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) all = all && b[k] != kUnpublished;
+    if (all) break;
+    if (!keep_waiting(it, abort_flag, status)) {
+      ok = false;
+      break;
+    }
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+      const int e = t + k * kPanelThreads;
+      if (e < total && b[k] == kUnpublished) b[k] = peek(src(e));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MAXW; ++k) {
+    const int e = t + k * kPanelThreads;
+    if (e < total) put(e, __longlong_as_double((long long)b[k]));
+  }
+  return ok;
+}
+
+// Cholesky G = R^T R of the leading n x n block and R^{-1}, all threads of the
+// workgroup, one barrier per column.  On entry A holds G (upper part read); on
+// exit R's strict upper part is stored transposed in A's strict lower part
+// (A[j][k] = R[k][j], j > k), its diagonal in diag[], and Minv holds R^{-1}
+// (upper, zero elsewhere).  Column k of R^{-1} follows from the columns before
+// it: Minv[i][k] = -(sum_{l=i}^{k-1} Minv[i][l] R[l][k]) / R[k][k].  Returns
+// false when a pivot is not positive or not finite (same value in all threads).
+RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
+  const int g = t & 15, row = t >> 4;
+  for (int e = t; e < kPC * kLd; e += kPanelThreads) Minv[e] = 0.0;
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < n; ++k) {
+    const double d = A[k * kLd + k];
+    ok = ok && (d > 0.0) && (d < 1.7976931348623157e308);
+    const double rkk = sqrt(d);
+    const double rinv = 1.0 / rkk;
+    const double dinv = 1.0 / d;
+    // trailing update of the upper part: A[i][j] -= A[k][i] A[k][j] / d, k < i <= j < n
+#pragma unroll
+    for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
+      const int e = t + q * kPanelThreads;
+      const int i = e >> 6, j = e & 63;
+      if (i > k && j >= i && j < n) A[i * kLd + j] -= A[k * kLd + i] * A[k * kLd + j] * dinv;
+    }
+    // row k of R, stored transposed below the diagonal
+    if (t > k && t < n) A[t * kLd + k] = A[k * kLd + t] * rinv;
+    if (t == 0) diag[k] = rkk;
+    // column k of R^{-1}: 16 lanes per row
+    double acc = 0.0;
+    for (int l = row + g; l < k; l += 16) acc += Minv[row * kLd + l] * A[k * kLd + l];
+    acc = row16_sum(acc);
+    if (g == 0) {
+      if (row < k)
+        Minv[row * kLd + k] = -acc * rinv;
+      else if (row == k)
+        Minv[k * kLd + k] = rinv;
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// LU factorization without pivoting of the leading n x n block of A = Q11 - S,
+// with S[k] = -sign(pivot) chosen at step k (so |U[k][k]| >= 1), plus U^{-1}
+// (Z) and L^{-1} (W, unit lower).  On exit A holds U's strict upper part and
+// the unscaled multipliers below the diagonal (L[i][k] = A[i][k] rcp[k]);
+// udiag[k] = U[k][k], rcp[k] = 1 / U[k][k], sgn[k] = S[k].  One barrier per
+// step; row k of W and column k of Z follow from the rows/columns before them.
+RQ_DEV void lu_signed(double* A, double* Z, double* W, double* sgn, double* udiag, double* rcp,
+                      int n, int t) {
+  const int g = t & 15, row = t >> 4;
+  for (int e = t; e < kPC * kLd; e += kPanelThreads) {
+    Z[e] = 0.0;
+    W[e] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double p = A[k * kLd + k];
+    const double sk = (p >= 0.0) ? -1.0 : 1.0;
+    const double ukk = p - sk;
+    const double uinv = 1.0 / ukk;
+#pragma unroll
+    for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
+      const int e = t + q * kPanelThreads;
+      const int i = e >> 6, j = e & 63;
+      if (i > k && j > k && i < n && j < n) A[i * kLd + j] -= A[i * kLd + k] * uinv * A[k * kLd + j];
+    }
+    if (t == 0) {
+      sgn[k] = sk;
+      udiag[k] = ukk;
+      rcp[k] = uinv;
+    }
+    // column k of U^{-1} (rows row < k) and row k of L^{-1} (columns row < k)
+    double az = 0.0, aw = 0.0;
+    for (int l = row + g; l < k; l += 16) {
+      az += Z[row * kLd + l] * A[l * kLd + k];
+      aw += A[k * kLd + l] * rcp[l] * W[l * kLd + row];
+    }
+    az = row16_sum(az);
+    aw = row16_sum(aw);
+    if (g == 0) {
+      if (row < k) {
+        Z[row * kLd + k] = -az * uinv;
+        W[k * kLd + row] = -aw;
+      } else if (row == k) {
+        Z[k * kLd + k] = uinv;
+        W[k * kLd + k] = 1.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The 16 waves of the workgroup each own one 16 x 16 block (p, q) of a 64 x 64
+// result (p = wave / 4, q = wave % 4); lane l then holds rows 16 p + l/16 + 4 v,
+// column 16 q + l % 16 (v = accumulator element), the FP64 MFMA output layout.
+// Gram of a 64-row chunk X (LDS, row-major): acc += X[:, p-block]^T X[:, q-block].
+RQ_DEV dx4 gram_chunk(const double* X, dx4 acc, int p, int q, int lane) {
+#pragma unroll
+  for (int k0 = 0; k0 < kPC; k0 += 4) {
+    const double* r = X + (k0 + (lane >> 4)) * kLd;
+    acc = mfma_f64(r[16 * p + (lane & 15)], r[16 * q + (lane & 15)], acc);
+  }
+  return acc;
+}
+// Product of a 64-row chunk X with a 64 x 64 matrix B (both LDS, row-major).
+RQ_DEV dx4 product_chunk(const double* X, const double* B, int p, int q, int lane) {
+  dx4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < kPC; k0 += 4) {
+    const double a = X[(16 * p + (lane & 15)) * kLd + k0 + (lane >> 4)];
+    const double b = B[(k0 + (lane >> 4)) * kLd + 16 * q + (lane & 15)];
+    acc = mfma_f64(a, b, acc);
+  }
+  return acc;
+}
+
+// x <- x B for this workgroup's 256 x 64 tile (held as x[i] = row g + 16 i of
+// column c), staged through X in four chunks of 64 rows.  Rows of the panel
+// below `keep_below` (global index) keep their values.
+RQ_DEV void tile_times(double (&x)[kPR], double* X, const double* B, int t, int rbase,
+                       int keep_below) {
+  const int g = t % kPG, c = t / kPG, lane = t & 63, wave = t >> 6;
+  const int p = wave >> 2, q = wave & 3;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) X[(g + 16 * ii) * kLd + c] = x[4 * ch + ii];
+    __syncthreads();
+    const dx4 acc = product_chunk(X, B, p, q, lane);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[(16 * p + (lane >> 4) + 4 * v) * kLd + 16 * q + (lane & 15)] = acc[v];
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = rbase + g + 16 * (4 * ch + ii);
+      if (r >= keep_below) x[4 * ch + ii] = X[(g + 16 * ii) * kLd + c];
+    }
+    __syncthreads();
+  }
+}
+
+// Gram matrix of this workgroup's tile, published as record words (row-major).
+RQ_DEV void tile_gram(const double (&x)[kPR], double* X, double* rec, int t) {
+  const int g = t % kPG, c = t / kPG, lane = t & 63, wave = t >> 6;
+  const int p = wave >> 2, q = wave & 3;
+  dx4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) X[(g + 16 * ii) * kLd + c] = x[4 * ch + ii];
+    __syncthreads();
+    acc = gram_chunk(X, acc, p, q, lane);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    publish(rec + (16 * p + (lane >> 4) + 4 * v) * kPC + 16 * q + (lane & 15), acc[v]);
+}
+
+// Sum of the workgroups' Gram matrices: reduce-scatter (workgroup w sums its
+// slice of the entries over all records, in workgroup order) through `part`,
+// then every workgroup gathers the whole sum into G (LDS, row-major).
+RQ_DEV bool gram_allreduce(const double* recs, double* red, double* G, double* stage, int nwg,
+                           int wg, int t, uint32_t* abort_flag, int64_t* status) {
+  const int S = (kWords + nwg - 1) / nwg;
+  const int lo = wg * S;
+  const int len = max(0, min(kWords, lo + S) - lo);
+  const int ln = max(len, 1);
+  bool ok = wait_words<5>([&](int e) { return recs + (int64_t)(e / ln) * kWords + lo + e % ln; },
+                          nwg * len, [&](int e, double v) { stage[e] = v; }, t, abort_flag, status);
+  if (__syncthreads_or(!ok)) return false;
+  for (int e = t; e < len; e += kPanelThreads) {
+    double sum = 0.0;
+    for (int w = 0; w < nwg; ++w) sum += stage[w * len + e];
+    publish(red + lo + e, sum);
+  }
+  ok = wait_words<kWords / kPanelThreads>([&](int e) { return red + e; }, kWords,
+                                          [&](int e, double v) { G[(e >> 6) * kLd + (e & 63)] = v; },
+                                          t, abort_flag, status);
+  return !__syncthreads_or(!ok);
+}
+
+
+__global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a) {
+  const int t = threadIdx.x;
+  const int g = t % kPG;           // row group
+  const int c = t / kPG;           // column
+  const int wg = blockIdx.x;
+  const int rbase = wg * kPanelRows;
+  const int bj = a.bj;
+  const bool colok = c < bj;
+  if (prior_timeout(a.status)) return;
+
+  // LDS: four 64 x 64 regions shared by the two routes, plus small vectors
+  __shared__ double s_reg[4][kRegion];
+  __shared__ double s_bc[2][kPanelRows];   // column j (before its reflection), by step parity
+  __shared__ double s_vec[5][kPC];
+  double* const s_tau = s_vec[0];
+  double (*const s_T)[kLd] = reinterpret_cast<double (*)[kLd]>(s_reg[1]);
+
+  double x[kPR];
+#pragma unroll
+  for (int i = 0; i < kPR; ++i) {
+    const int r = rbase + g + kPG * i;
+    x[i] = (colok && r < a.M) ? canonical(a.A[r + (int64_t)c * a.lda]) : 0.0;
+  }
+
+  {
+    // ---------------- two-pass Cholesky QR and reconstruction ----------------
+    double* const G = s_reg[0];
+    double* const RB = s_reg[1];
+    double* const X = s_reg[2];
+    double* const D = s_reg[3];
+    double* const diag = s_vec[1];
+    double* const rcp = s_vec[2];
+    double* const sgn = s_vec[3];
+    double* const udiag = s_vec[4];
+    double* const e1 = a.crec;                                   // [nwg][4096] Gram parts
+    double* const e2 = e1 + (int64_t)a.nwg * kWords;             // [4096] Gram sum
+    double* const e3 = e2 + kWords;                              // second pass
+    double* const e4 = e3 + (int64_t)a.nwg * kWords;
+    double* const e5 = e4 + kWords;                              // [4096 + 64] U^{-1}, S
+    // pass 1
+    tile_gram(x, X, e1 + (int64_t)wg * kWords, t);
+    if (!gram_allreduce(e1, e2, G, X, a.nwg, wg, t, a.abort_flag, a.status)) return;
+    bool good = chol_inv(G, D, diag, bj, t);
+    double dmax = 0.0, dmin = 1.7976931348623157e308;
+    for (int k = 0; k < bj; ++k) {
+      dmax = fmax(dmax, diag[k]);
+      dmin = fmin(dmin, diag[k]);
+    }
+    good = good && dmax <= kCondMax * dmin;
+    if (!good) {
+      // every workgroup reaches the same decision; the panel is untouched
+      if (wg == 0 && t == 0) *a.fallback = 1u;
+      return;
+    }
+    {
+      // R1 in upper form into RB (read by R = R2 R1 in workgroup 0)
+      for (int e = t; e < kPC * kPC; e += kPanelThreads) {
+        const int i = e >> 6, j = e & 63;
+        RB[i * kLd + j] = (i < bj && j < bj) ? (i == j ? diag[i] : (j > i ? G[j * kLd + i] : 0.0)) : 0.0;
+      }
+      tile_times(x, X, D, t, rbase, 0);                          // Q1 = X R1^{-1}
+      // pass 2
+      tile_gram(x, X, e3 + (int64_t)wg * kWords, t);
+      if (!gram_allreduce(e3, e4, G, X, a.nwg, wg, t, a.abort_flag, a.status)) return;
+      if (!chol_inv(G, D, diag, bj, t) && t == 0) raise_status(a.status, kErrNonFinite);
+      tile_times(x, X, D, t, rbase, 0);                          // Q = Q1 R2^{-1}
+      if (wg == 0) {
+        // R = R2 R1 into D (R2 upper: diag and G's lower part transposed)
+        for (int e = t; e < kPC * kPC; e += kPanelThreads) {
+          const int i = e >> 6, j = e & 63;
+          double s = 0.0;
+          if (i < bj && j < bj && i <= j)
+            for (int k = i; k <= j; ++k) s += (k == i ? diag[i] : G[k * kLd + i]) * RB[k * kLd + j];
+          D[i * kLd + j] = s;
+        }
+        __syncthreads();                                         // G (R2) is overwritten next
+        // Q11 into G, then its signed LU with U^{-1} in X and L^{-1} in RB
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) G[(g + 16 * ii) * kLd + c] = x[ii];
+        __syncthreads();
+        lu_signed(G, X, RB, sgn, udiag, rcp, bj, t);
+        for (int e = t; e < kWords; e += kPanelThreads) publish(e5 + e, X[(e >> 6) * kLd + (e & 63)]);
+        if (t < kPC) publish(e5 + kWords + t, t < bj ? sgn[t] : 0.0);
+        // T = -U S L^{-T}: T[i][j] = -sum_{k=i..j} U[i][k] S[k] W[j][k]
+        double tv[kPC * kPC / kPanelThreads];
+#pragma unroll
+        for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
+          const int e = t + q * kPanelThreads;
+          const int i = e >> 6, j = e & 63;
+          double s = 0.0;
+          if (i < bj && j < bj && i <= j)
+            for (int k = i; k <= j; ++k) s += (k == i ? udiag[i] : G[i * kLd + k]) * sgn[k] * RB[j * kLd + k];
+          tv[q] = -s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
+          const int e = t + q * kPanelThreads;
+          RB[(e >> 6) * kLd + (e & 63)] = tv[q];
+        }
+        if (t < bj) {
+          s_tau[t] = -udiag[t] * sgn[t];
+          a.tau[t] = s_tau[t];
+        }
+        // rows 0..bj-1: S R above and on the diagonal, L below
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int r = g + 16 * ii;
+          if (r < bj && colok)
+            x[ii] = (r <= c) ? sgn[r] * D[r * kLd + c] : G[r * kLd + c] * rcp[c];
+        }
+        __syncthreads();
+      }
+      bool okw = true;
+      if (wg != 0)
+        okw = wait_words<5>([&](int e) { return e5 + e; }, kWords + kPC,
+                            [&](int e, double v) {
+                              if (e < kWords)
+                                X[(e >> 6) * kLd + (e & 63)] = v;
+                              else
+                                sgn[e - kWords] = v;
+                            },
+                            t, a.abort_flag, a.status);
+      if (__syncthreads_or(!okw)) return;
+      // Y = Q U^{-1} below row bj
+      tile_times(x, G, X, t, rbase, bj);
+    }
+  }
+
+  // ---- write back: R / reflector tails into the panel, explicit Y, T --------
+#pragma unroll
+  for (int i = 0; i < kPR; ++i) {
+    const int r = rbase + g + kPG * i;
+    if (r < a.M) {
+      if (colok) a.A[r + (int64_t)c * a.lda] = x[i];
+      const double yv = colok ? ((r < c) ? 0.0 : (r == c ? 1.0 : x[i])) : 0.0;
+      a.Y[r + (int64_t)c * a.ldy] = yv;
+    }
+  }
+  if (wg == 0 && a.T) {
+    for (int e = t; e < bj * bj; e += kPanelThreads) {
+      const int i = e % bj, q = e / bj;
+      a.T[i + (int64_t)q * a.ldt] = (i <= q) ? s_T[i][q] : 0.0;
+    }
+  }
+}
+
 
 __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   const int t = threadIdx.x;
@@ -37,12 +425,14 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   const int bj = a.bj;
   const bool colok = c < bj;
   if (prior_timeout(a.status)) return;
+  if (a.fallback && *a.fallback == 0u) return;   // the Cholesky-QR route produced the panel
 
+  // LDS: four 64 x 64 regions shared by the two routes, plus small vectors
+  __shared__ double s_reg[4][kRegion];
   __shared__ double s_bc[2][kPanelRows];   // column j (before its reflection), by step parity
-  __shared__ double s_S[kPC][kPC + 1];     // workgroup 0: S[q][i] = y_q^T y_i for q < i
-  __shared__ double s_tau[kPC];
-  __shared__ double s_words[2 * kRC * kPC + kPC];   // one chunk of record words
-  __shared__ double s_T[kPC][kPC + 1];
+  __shared__ double s_vec[5][kPC];
+  double* const s_tau = s_vec[0];
+  double (*const s_T)[kLd] = reinterpret_cast<double (*)[kLd]>(s_reg[1]);
 
   double x[kPR];
 #pragma unroll
@@ -50,11 +440,14 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
     const int r = rbase + g + kPG * i;
     x[i] = (colok && r < a.M) ? canonical(a.A[r + (int64_t)c * a.lda]) : 0.0;
   }
-  if (wg == 0) {
-    for (int e = t; e < kPC * (kPC + 1); e += kPanelThreads) (&s_T[0][0])[e] = 0.0;
-  }
-  double prev_scale = 0.0;
 
+  {
+  if (wg == 0) {
+    for (int e = t; e < kPC * kLd; e += kPanelThreads) (&s_T[0][0])[e] = 0.0;
+  }
+  double (*const s_S)[kLd] = reinterpret_cast<double (*)[kLd]>(s_reg[0]);
+  double* const s_words = s_reg[2];
+  double prev_scale = 0.0;
   for (int j = 0; j <= bj; ++j) {
     const int buf = j & 1;
     // ---- publish column j of this workgroup's rows ----------------------------
@@ -219,6 +612,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
       __syncthreads();
     }
   }
+  }
   // ---- write back: R / reflector tails into the panel, explicit Y, T --------
 #pragma unroll
   for (int i = 0; i < kPR; ++i) {
@@ -237,7 +631,13 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
   }
 }
 
+
 hipError_t launch_panel(const PanelArgs& a, hipStream_t s) {
+  if (a.crec) {
+    hipLaunchKernelGGL(panel_cholqr_kernel, dim3(a.nwg), dim3(kPanelThreads), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(panel_kernel, dim3(a.nwg), dim3(kPanelThreads), 0, s, a);
   return hipGetLastError();
 }
