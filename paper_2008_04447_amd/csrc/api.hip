@@ -115,9 +115,10 @@ size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n) {
 }
 
 rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, double* out,
-                               int64_t ldout) {
+                               int64_t ldout, __bf16* lbf) {
   int ks, kc;
   plan_split32(g.K, g.N, &ks, &kc);
+  g.lbf = lbf;
   g.ksplit = ks;
   g.kchunk = kc;
   const double fl = 2.0 * g.P * (double)g.K * g.N;
@@ -144,7 +145,8 @@ rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, 
 }
 
 rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
-                      const float* A, int64_t lda, double* B, int64_t ldb, double* part) {
+                      const float* A, int64_t lda, double* B, int64_t ldb, double* part,
+                      __bf16* lbf) {
   GemmArgsF g{};
   g.L = Omega;
   g.sLp = 1;
@@ -154,7 +156,7 @@ rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* 
   g.P = ell;
   g.K = (int)m;
   g.N = (int)n;
-  return gemm_lx_bf16_reduced(h, K_SKETCH, g, part, B, ldb);
+  return gemm_lx_bf16_reduced(h, K_SKETCH, g, part, B, ldb, lbf);
 }
 
 size_t sq_rec_doubles(int ell, int64_t N) {
@@ -377,12 +379,14 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
   DeviceGuard guard(h->device);
   const size_t np = std::max(sketch_part_doubles((int)ell, m, n),
                              sketch_part_doubles_bf16((int)ell, m, n));
-  RQ_TRY(reserve(h, padded_bytes(np)));
+  const size_t nl = bf16_stage_doubles(m);
+  RQ_TRY(reserve(h, padded_bytes(np) + padded_bytes(nl)));
   Carve cv(h->ws);
   double* part = cv.take<double>(np);
+  __bf16* lbf = reinterpret_cast<__bf16*>(cv.take<double>(nl));
   if (prec == RQ_MIXED_BF16)
     return sketch_bf16(h, (int)ell, m, n, Omega, ldo, static_cast<const float*>(A), lda, B, ldb,
-                       part);
+                       part, lbf);
   return sketch_fp64(h, (int)ell, m, n, Omega, ldo, static_cast<const double*>(A), lda, B, ldb,
                      part);
 }

@@ -144,10 +144,13 @@ rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* 
                       const double* A, int64_t lda, double* B, int64_t ldb, double* part);
 // B = Omega A with A FP32 on BF16 MFMA (split-K partials summed in FP64).
 rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* Omega, int64_t ldo,
-                      const float* A, int64_t lda, double* B, int64_t ldb, double* part);
+                      const float* A, int64_t lda, double* B, int64_t ldb, double* part,
+                      __bf16* lbf);
 // Y^T-style product with FP32 X on BF16 MFMA, reduced into out (leading dim ldout).
 rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, double* out,
-                               int64_t ldout);
+                               int64_t ldout, __bf16* lbf);
+// doubles of workspace that hold the BF16 staging of an operand with K columns
+inline size_t bf16_stage_doubles(int64_t K) { return (size_t)(bf16_stage_elems(K) + 3) / 4; }
 size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm);

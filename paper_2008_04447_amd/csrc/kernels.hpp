@@ -72,7 +72,12 @@ struct GemmArgsF {
   int ksplit, kchunk;                  // kchunk a multiple of 32
   double* out; int64_t ldout; int64_t split_stride;   // partial s at out + s * split_stride
   const int64_t* xcol = nullptr;       // optional column map of X
+  __bf16* lbf = nullptr;               // workspace: at least bf16_stage_elems(K) BF16 values
+  int kpad = 0;                        // set by the launcher
 };
+int bf16_stage_kpad(int K);
+inline int64_t bf16_stage_elems(int64_t K) { return (int64_t)96 * (((K + 31) / 32) * 32 + 32); }
+// Stages L as BF16 into g.lbf, then runs the contraction (two kernels on stream s).
 hipError_t launch_gemm_lx_bf16(const GemmArgsF& g, hipStream_t s);
 // C(M x N) = Y(M x K) Z(K x N) with Y FP32 and Z FP64, both rounded to BF16.
 hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float* Y, int64_t ldy,

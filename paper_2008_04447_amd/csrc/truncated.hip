@@ -30,6 +30,7 @@ struct TrWork {
   double* tblk;     // 64 x 64
   double* mhat;     // 64 x 64
   double* part;     // split-K partials
+  __bf16* lbf;      // BF16 staging of the left operand (mixed path)
 };
 
 static size_t split_part_bound(int64_t n, int64_t k) {
@@ -42,7 +43,7 @@ static size_t trwork_doubles(int64_t m, int64_t n, int64_t k, int ell) {
   const int64_t mn = std::max(m, n);   // the QR of Z0^T in TUXV has n rows
   return padded_bytes((size_t)ell * n) + padded_bytes((size_t)k * n) + padded_bytes((size_t)m * 64) +
          padded_bytes((size_t)mn * 64) + padded_bytes(panel_rec_doubles(mn)) +
-         padded_bytes(sq_rec_doubles(ell, n)) +
+         padded_bytes(sq_rec_doubles(ell, n)) + padded_bytes(bf16_stage_doubles(mn)) +
          padded_bytes((size_t)64 * n) + padded_bytes((size_t)64 * k) + padded_bytes((size_t)k * 64) +
          2 * padded_bytes(64 * 64) + padded_bytes(split_part_bound(n, k)) + 4 * 64 * sizeof(int) + 4096;
 }
@@ -61,6 +62,7 @@ static TrWork carve_trwork(Carve& cv, int64_t m, int64_t n, int64_t k, int ell) 
   w.tblk = cv.take<double>(64 * 64);
   w.mhat = cv.take<double>(64 * 64);
   w.part = cv.take<double>(split_part_bound(n, k));
+  w.lbf = reinterpret_cast<__bf16*>(cv.take<double>(bf16_stage_doubles(std::max(m, n))));
   w.sw.src_top = cv.take<int>(64);
   w.sw.dst_low = cv.take<int>(64);
   return w;
@@ -113,7 +115,7 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
   const double* A = static_cast<const double*>(Av);
   const float* Af = static_cast<const float*>(Av);
   if (f32)
-    RQ_TRY(sketch_bf16(h, ell, m, n, Omega, ldo, Af, lda, w.sample, ell, w.part));
+    RQ_TRY(sketch_bf16(h, ell, m, n, Omega, ldo, Af, lda, w.sample, ell, w.part, w.lbf));
   else
     RQ_TRY(sketch_fp64(h, ell, m, n, Omega, ldo, A, lda, w.sample, ell, w.part));
   for (int64_t col0 = 0; col0 < k; col0 += b) {
@@ -177,7 +179,7 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
         g.P = bj;
         g.K = (int)M;
         g.N = (int)Nt;
-        RQ_TRY(gemm_lx_bf16_reduced(h, K_INNER, g, w.part, w.sbuf, 64));
+        RQ_TRY(gemm_lx_bf16_reduced(h, K_INNER, g, w.part, w.sbuf, 64, w.lbf));
       } else {
         GemmArgs g{};
         g.L = w.ybuf;

@@ -1,0 +1,97 @@
+"""The two panel routes of the RQRCP block loop against the FP64 oracle.
+
+Panels whose first Cholesky factor is well conditioned are factored by two
+passes of Cholesky QR followed by Householder reconstruction; the others by the
+column-by-column Householder loop.  Both must reproduce the oracle's pivots,
+R, tau and T (Section 2 reflections, Algorithm 4).  Which route a panel takes
+is fixed by the inputs: the tests check the conditioning of the oracle's panels
+on the CPU so that each route is known to be exercised.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from test_gpu_rqrcp import ABS, REL, _check_against_oracle, _rqrcp_case, api  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+GATE = 16384.0          # largest/smallest diagonal of the first Cholesky factor
+
+
+def _panel_diag_ratios(a, om, b, p, k):
+    """max/min |R_jj| of each block of the oracle's factorization (pivoted)."""
+    ref = oracle.rqrcp(a, om, b, p, k=k)
+    d = np.abs(np.diag(ref.qr[:k, :k]))
+    return [d[c:c + b].max() / d[c:c + b].min() for c in range(0, k, b)]
+
+
+def _apply_q(qr, tau, x):
+    """H_1 ... H_k x for the reflectors stored below the diagonal of qr."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    for j in reversed(range(len(tau))):
+        v = np.concatenate(([1.0], qr[j + 1:, j]))
+        x[j:] -= tau[j] * np.outer(v, v @ x[j:])
+    return x
+
+
+def _check_tall(a, om, b, p, k, qr, jpvt, tau, T):
+    """Oracle comparison for tall panels without forming the m x m Q."""
+    m, n = a.shape
+    ref = oracle.rqrcp(a, om, b, p, k=k)
+    pre = ref.trace.prefix(ref.sample_scale, REL, ABS)
+    assert sorted(jpvt) == list(range(n))
+    np.testing.assert_array_equal(jpvt[:pre], ref.jpvt[:pre])
+    rows = min(pre, k)
+    d = np.linalg.norm(np.triu(qr[:k])[:rows] - np.triu(ref.qr[:k])[:rows], axis=1)
+    nrm = np.linalg.norm(np.triu(ref.qr[:k])[:rows], axis=1)
+    assert np.all(d <= 1e-10 * nrm + 1e-12 * np.linalg.norm(a))
+    if pre >= k:
+        np.testing.assert_allclose(tau, ref.tau, atol=1e-10)
+    r_full = np.triu(qr)
+    r_full[k:, k:] = qr[k:, k:]
+    qk = _apply_q(qr, tau, np.eye(m, k))
+    assert np.linalg.norm(qk.T @ qk - np.eye(k), 2) <= 1e-13
+    ap = a[:, jpvt]
+    assert np.linalg.norm(ap - _apply_q(qr, tau, r_full)) / np.linalg.norm(a) <= 1e-13
+    col0 = 0
+    while col0 < k:
+        bj = min(b, k - col0)
+        y = oracle.unit_lower(qr[col0:, col0:col0 + bj], bj)
+        np.testing.assert_allclose(T[:bj, col0:col0 + bj], oracle.form_t(y, tau[col0:col0 + bj]),
+                                   atol=1e-12)
+        col0 += bj
+
+
+def test_routes_mixed_in_one_factorization(api):
+    """Block 1: 64 large Gaussian columns (Cholesky QR); later blocks: steeply
+    graded columns (column-by-column route)."""
+    m, b, p = 600, 64, 8
+    g = synth.gaussian((m, 64), 5100) * 1e3
+    h, _ = synth.graded_known_pivots(m, 128, 5101, ratio=0.8, eta=1e-3)
+    a = np.asfortranarray(np.hstack([g, h]))
+    n = a.shape[1]
+    om = synth.omega(b + p, m, 5102)
+    ratios = _panel_diag_ratios(a, om, b, p, n)
+    assert ratios[0] <= GATE / 10 and min(ratios[1:]) >= GATE * 10, ratios
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, n, a, om)
+    _check_against_oracle(a, om, b, p, n, qr, jpvt, tau, T, min_prefix=64)
+
+
+@pytest.mark.parametrize("m,n,b", [
+    (51200, 96, 64),     # 200 workgroups: some reduce-scatter slices are empty
+    (700, 130, 64),      # 3 workgroups: a slice larger than the workgroup
+    (90, 90, 48),        # one workgroup, ragged last block
+])
+def test_cholqr_route_shapes(api, m, n, b):
+    p = 8
+    a = synth.gaussian((m, n), 5200 + m)
+    om = synth.omega(b + p, m, 5201 + n)
+    ratios = _panel_diag_ratios(a, om, b, p, min(m, n))
+    assert max(ratios[:-1] or [0.0]) <= GATE / 10, ratios
+    k = min(m, n)
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, k, a, om)
+    if m > 4000:
+        _check_tall(a, om, b, p, k, qr, jpvt, tau, T)
+    else:
+        _check_against_oracle(a, om, b, p, k, qr, jpvt, tau, T, min_prefix=1)
