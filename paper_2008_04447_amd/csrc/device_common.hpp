@@ -86,6 +86,30 @@ RQ_DEV unsigned long long peek(const double* p) {
 
 RQ_DEV double canonical(double v) { return (v != v) ? __builtin_nan("") : v; }
 
+// 1/sqrt(d) and 1/u for d > 0, u != 0 from the hardware estimates refined by
+// one Newton step: a few dependent operations instead of the long IEEE sqrt
+// and divide sequences, on the serial chains of the pivot and panel steps.
+// Every workgroup runs the same sequence, so all derive the same bits.
+RQ_DEV double rsqrt_nr(double d) {
+  const double y = __builtin_amdgcn_rsq(d);
+  return y * fma(-0.5 * d * y, y, 1.5);
+}
+RQ_DEV double rcp_nr(double u) {
+  const double y = __builtin_amdgcn_rcp(u);
+  return y * fma(-u, y, 2.0);
+}
+
+// Reflector of a column with leading entry alpha and squared 2-norm s2 > 0
+// (Section 2): beta = -sign(alpha) sqrt(s2) with sign(0) = +1, the tail scale
+// 1 / (alpha - beta) and tau = (beta - alpha) / beta.
+RQ_DEV void reflector_coeffs(double alpha, double s2, double& beta, double& scale, double& tau) {
+  const double r = rsqrt_nr(s2);
+  const double sn = s2 * r;
+  beta = (alpha >= 0.0) ? -sn : sn;
+  scale = rcp_nr(alpha - beta);
+  tau = (beta - alpha) * ((alpha >= 0.0) ? -r : r);
+}
+
 // One bounded wait iteration: false (and the abort flag set) once the wait has
 // lasted kSpinLimit polls or another workgroup aborted (checked every 64 polls,
 // so the common short wait costs no extra round trip).

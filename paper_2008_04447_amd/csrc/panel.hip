@@ -97,9 +97,9 @@ RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
   for (int k = 0; k < n; ++k) {
     const double d = A[k * kLd + k];
     ok = ok && (d > 0.0) && (d < 1.7976931348623157e308);
-    const double rkk = sqrt(d);
-    const double rinv = 1.0 / rkk;
-    const double dinv = 1.0 / d;
+    const double rinv = rsqrt_nr(d);
+    const double rkk = d * rinv;
+    const double dinv = rinv * rinv;
     // trailing update of the upper part: A[i][j] -= A[k][i] A[k][j] / d, k < i <= j < n
 #pragma unroll
     for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
@@ -143,7 +143,7 @@ RQ_DEV void lu_signed(double* A, double* Z, double* W, double* sgn, double* udia
     const double p = A[k * kLd + k];
     const double sk = (p >= 0.0) ? -1.0 : 1.0;
     const double ukk = p - sk;
-    const double uinv = 1.0 / ukk;
+    const double uinv = rcp_nr(ukk);
 #pragma unroll
     for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
       const int e = t + q * kPanelThreads;
@@ -562,10 +562,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
     const double s2 = sgj;
     double beta = 0.0, tau = 0.0, scale = 0.0;
     if (s2 > 0.0) {
-      const double sn = sqrt(s2);
-      beta = (alpha >= 0.0) ? -sn : sn;
-      scale = 1.0 / (alpha - beta);
-      tau = (beta - alpha) / beta;
+      reflector_coeffs(alpha, s2, beta, scale, tau);
     } else if (!(s2 == 0.0)) {
       if (t == 0) raise_status(a.status, kErrNonFinite);
     }

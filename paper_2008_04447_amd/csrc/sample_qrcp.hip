@@ -196,10 +196,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
     const double alpha = col[j];
     double beta = 0.0, tau = 0.0, scale = 0.0;
     if (s2 > 0.0) {
-      const double sn = sqrt(s2);
-      beta = (alpha >= 0.0) ? -sn : sn;
-      scale = 1.0 / (alpha - beta);
-      tau = (beta - alpha) / beta;
+      reflector_coeffs(alpha, s2, beta, scale, tau);
     }
     // ---- positions: j <-> wpos ----------------------------------------------
     if (active) {
@@ -246,7 +243,10 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
       nu2 = column_sum<kQ>(n0 + n1);
     }
-    __syncthreads();   // s_all and the wave winners are rewritten in the next step
+    // No barrier here: the next step rewrites s_wv only after this step's
+    // __syncthreads_or (which follows every read of s_wv), and s_all only after
+    // its own first barrier (which follows this step's last read of s_all);
+    // s_v belongs to one wave.
   }
   // Every workgroup loaded its columns before the first barrier, so the
   // in-place write of the permuted sample cannot overwrite unread input.
