@@ -542,13 +542,19 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     }
     // 5. A_trailing -= Y Z.  Rows 0..bj-1 (R12) are updated first on the main
     // stream: the sample update and the next block's sample QRCP need only them.
-    // The other rows are updated on the side stream meanwhile; the next block
-    // waits for them before it permutes and factors its panel.
+    // The other rows are updated on the side stream, started only after the
+    // sample update so that the short kernels on the main stream run without
+    // contention; the next block waits for them before it permutes and factors
+    // its panel.
     {
       KTimer kt(h, K_UPDATE, 2.0 * bj * (double)bj * Nt,
                 8.0 * (2.0 * bj * Nt + (double)bj * bj + (double)bj * Nt));
       RQ_CHECK(h, launch_update(Ctr, lda, bj, (int)Nt, ybuf, m, zbuf, 64, bj, s));
     }
+    // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
+    if (col0 + bj < k)
+      RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
+                               mhat));
     if (M > bj) {
       RQ_CHECK(h, hipEventRecord(h->ev_z, s));
       RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_z, 0));
@@ -562,10 +568,6 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_CHECK(h, hipEventRecord(h->ev_u, h->side));
       pending_rows = true;
     }
-    // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
-    if (col0 + bj < k)
-      RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
-                               mhat));
   }
   if (pending_rows) RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
   return RQ_OK;
