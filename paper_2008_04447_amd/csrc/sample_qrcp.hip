@@ -12,6 +12,10 @@
 // published column and applies it to its own columns.  Norms of rows j+1.. are
 // recomputed from the transformed columns (no downdating).  Ties go to the
 // lowest current position; positions follow the transpositions j <-> p_j.
+// Work that is the same for the whole workgroup (its record, the winner, the
+// reflector's coefficients) is done by wave 0 alone and shared through LDS: with
+// four waves per SIMD, repeating it in every wave would cost four times its
+// latency on every step.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -46,9 +50,11 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   if (prior_timeout(a.status)) return;
 
   __shared__ double s_wv[kSqWaves];
-  __shared__ int s_wp[kSqWaves], s_ww[kSqWaves];
+  __shared__ int s_wp[kSqWaves];
+  __shared__ double s_cand[kSqWaves][LM];      // each wave's best column
   __shared__ double s_all[kSpecCap];
-  __shared__ double s_v[kSqWaves][LM];         // each wave's copy of the reflector
+  __shared__ double s_hh[3];                   // beta, scale, tau of the step's reflector
+  __shared__ int s_hp[2];                      // winner position, its record (-2: timed out)
 
   double x[RPL];
 #pragma unroll
@@ -72,9 +78,22 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   bool active = own;
   bool flagged = false;
 
+  // Record words this thread polls in every step: all candidates (value,
+  // position) and, when they fit in LDS, their columns.  The offsets within a
+  // step's records are the same for every step.
+  const bool spec = a.nwg * (LM + 2) <= kSpecCap;
+  const int per = spec ? LM + 2 : 2;
+  const int total = a.nwg * per;
+  int off[kPoll];
+#pragma unroll
+  for (int k = 0; k < kPoll; ++k) {
+    const int e = t + k * kSqThreads;
+    const int w = e / per, f = e - w * per;
+    off[k] = (e < total) ? w * a.rs + f : -1;
+  }
+
   for (int j = 0; j < a.steps; ++j) {
-    // ---- local best candidate: wave reduction, then every wave reduces the
-    // 16 wave winners itself (no single-thread pass, no extra barrier) -------
+    // ---- each wave's best column (its values go to LDS) ---------------------
     const bool lead = active && q == 0;
     double bv = lead ? nu2 : -1.0;
     int bp = lead ? pos : INT_MAX;
@@ -84,45 +103,40 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       flagged = true;
     }
     wave_argmax(bv, bp, who);
+    if (bp != INT_MAX && cl == who) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) s_cand[wave][q + kQ * i] = x[i];
+    }
     if (lane == 0) {
       s_wv[wave] = bv;
       s_wp[wave] = bp;
-      s_ww[wave] = who;
     }
     __syncthreads();
-    {
+    // ---- wave 0 publishes the workgroup's record; the other waves go straight
+    // to polling (one wave doing this keeps the SIMDs free of repeated work)
+    if (wave == 0) {
       double v = (lane < kSqWaves) ? s_wv[lane] : -1.0;
       int p = (lane < kSqWaves) ? s_wp[lane] : INT_MAX;
-      int w = (lane < kSqWaves) ? s_ww[lane] : 0;
+      int w = lane;
       wave_argmax(v, p, w);
-      const int owner = (p == INT_MAX) ? -1 : w;
       double* rec = a.rec + ((int64_t)j * a.nwg + wg) * a.rs;
-      if (cl == owner) {
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) publish(rec + 2 + q + kQ * i, x[i]);
+      if (p != INT_MAX) {
+        for (int r = lane; r < LM; r += 64) publish(rec + 2 + r, s_cand[w][r]);
+      } else {
+        for (int r = lane; r < LM; r += 64) publish(rec + 2 + r, 0.0);
       }
-      if (owner < 0 && t < LM) publish(rec + 2 + t, 0.0);
-      if (t == 0) {
+      if (lane == 0) {
         publish(rec, v);
         publish(rec + 1, (double)p);
       }
     }
     // ---- exchange: wait for every workgroup's record of this step -------------
     const double* rj = a.rec + (int64_t)j * a.nwg * a.rs;
-    // all candidates (value, position) and, when they fit in LDS, their columns,
-    // each thread polling up to kPoll words at once
-    const bool spec = a.nwg * (LM + 2) <= kSpecCap;
-    const int per = spec ? LM + 2 : 2;
     bool ok = true;
     {
-      const int total = a.nwg * per;
       unsigned long long b[kPoll];
 #pragma unroll
-      for (int k = 0; k < kPoll; ++k) {
-        const int e = t + k * kSqThreads;
-        const int w = e / per, f = e - w * per;
-        b[k] = (e < total) ? peek(rj + (int64_t)w * a.rs + f) : 0ull;
-      }
+      for (int k = 0; k < kPoll; ++k) b[k] = (off[k] >= 0) ? peek(rj + off[k]) : 0ull;
       uint32_t it = 0;
       while (true) {
         bool all = true;
@@ -134,11 +148,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
           break;
         }
 #pragma unroll
-        for (int k = 0; k < kPoll; ++k) {
-          const int e = t + k * kSqThreads;
-          const int w = e / per, f = e - w * per;
-          if (e < total && b[k] == kUnpublished) b[k] = peek(rj + (int64_t)w * a.rs + f);
-        }
+        for (int k = 0; k < kPoll; ++k)
+          if (off[k] >= 0 && b[k] == kUnpublished) b[k] = peek(rj + off[k]);
       }
 #pragma unroll
       for (int k = 0; k < kPoll; ++k) {
@@ -147,9 +158,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
     }
     if (__syncthreads_or(!ok)) return;
-    // every wave finds the same winner and forms the same reflector
-    int wwg = 0, wpos;
-    {
+    // ---- wave 0 finds the winner and forms its reflector; the others wait -----
+    if (wave == 0) {
       double v = -1.0;
       int p = INT_MAX, w = 0;
       for (int i = lane; i < a.nwg; i += 64) {
@@ -162,42 +172,53 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
         }
       }
       wave_argmax(v, p, w);
-      wpos = p;
-      wwg = w;
+      bool okc = true;
+      if (p != INT_MAX && !spec) {
+        // columns did not fit: fetch the winner's column into the front of s_all
+        for (int r = lane; r < LM && okc; r += 64) {
+          const double* src = rj + (int64_t)w * a.rs + 2 + r;
+          unsigned long long bt = peek(src);
+          uint32_t it = 0;
+          while (bt == kUnpublished) {
+            if (!keep_waiting(it, a.abort_flag, a.status)) {
+              okc = false;
+              break;
+            }
+            bt = peek(src);
+          }
+          s_all[2 + r] = __longlong_as_double((long long)bt);
+        }
+        w = 0;
+        // lane 0 reads words other lanes of this wave wrote
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      const bool wave_ok = __builtin_amdgcn_ballot_w64(!okc) == 0;
+      if (lane == 0) {
+        s_hp[0] = p;
+        s_hp[1] = wave_ok ? w : -2;
+        if (p != INT_MAX && wave_ok) {
+          // the winner's value is the sum of squares of its rows j.., exactly
+          // the s2 its reflector needs
+          const double alpha = s_all[(spec ? w * (LM + 2) : 0) + 2 + j];
+          double beta = 0.0, tau = 0.0, scale = 0.0;
+          if (v > 0.0) reflector_coeffs(alpha, v, beta, scale, tau);
+          s_hh[0] = beta;
+          s_hh[1] = scale;
+          s_hh[2] = tau;
+        }
+      }
     }
+    __syncthreads();
+    const int wpos = s_hp[0], wwg = s_hp[1];
     if (wpos == INT_MAX) {          // every workgroup sees the same: consistent exit
       if (t == 0 && wg == 0) raise_status(a.status, kErrNoPivot);
       return;
     }
-    if (!spec) {
-      // columns did not fit: fetch the winner's column into the front of s_all
-      __syncthreads();
-      if (t < LM) {
-        const double* src = rj + (int64_t)wwg * a.rs + 2 + t;
-        unsigned long long bt = peek(src);
-        uint32_t it = 0;
-        while (bt == kUnpublished) {
-          if (!keep_waiting(it, a.abort_flag, a.status)) {
-            ok = false;
-            break;
-          }
-          bt = peek(src);
-        }
-        s_all[2 + t] = __longlong_as_double((long long)bt);
-      }
-      if (__syncthreads_or(!ok)) return;
-      wwg = 0;
-    }
+    if (wwg < 0) return;            // the winner's column never arrived (status raised)
+    const double beta = s_hh[0], scale = s_hh[1], tau = s_hh[2];
     const double* col = s_all + (spec ? wwg * (LM + 2) : 0) + 2;   // winner's column in LDS
-    double s2 = 0.0;
-    if (lane >= j && lane < LM) s2 += col[lane] * col[lane];
-    if (lane + 64 >= j && lane + 64 < LM) s2 += col[lane + 64] * col[lane + 64];
-    s2 = wave_sum(s2);
-    const double alpha = col[j];
-    double beta = 0.0, tau = 0.0, scale = 0.0;
-    if (s2 > 0.0) {
-      reflector_coeffs(alpha, s2, beta, scale, tau);
-    }
     // ---- positions: j <-> wpos ----------------------------------------------
     if (active) {
       if (pos == wpos) {
@@ -213,18 +234,15 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
     }
     // ---- apply the reflection to the remaining columns ---------------------------
-    // Each wave writes the reflector once into its own LDS row and reads it back
-    // (LDS operations of one wave complete in order; no workgroup barrier).
-    for (int r = lane; r < LM; r += 64) s_v[wave][r] = (r < j) ? 0.0 : (r == j ? 1.0 : col[r] * scale);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // The Householder vector is formed on the fly from the winner's column in LDS
+    // (every lane of a column group reads the same words: broadcast reads).
     if (active) {
       double v[RPL];
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        v[i] = s_v[wave][q + kQ * i];
+        const int r = q + kQ * i;
+        v[i] = (r < j) ? 0.0 : (r == j ? 1.0 : col[r] * scale);
         if (i & 1)
           d1 += v[i] * x[i];
         else
@@ -243,10 +261,10 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
       nu2 = column_sum<kQ>(n0 + n1);
     }
-    // No barrier here: the next step rewrites s_wv only after this step's
-    // __syncthreads_or (which follows every read of s_wv), and s_all only after
-    // its own first barrier (which follows this step's last read of s_all);
-    // s_v belongs to one wave.
+    // No barrier here: the next step rewrites s_wv, s_wp and s_cand only after
+    // this step's barriers (wave 0 read them before the first), s_all only
+    // after its own first barrier (which follows this step's last read of
+    // s_all), and s_hh, s_hp only after its own poll barrier.
   }
   // Every workgroup loaded its columns before the first barrier, so the
   // in-place write of the permuted sample cannot overwrite unread input.
