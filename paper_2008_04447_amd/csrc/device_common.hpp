@@ -152,7 +152,9 @@ constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16 lanes
 
 template <int kCtrl>
 RQ_DEV int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+  // every control used here reads a lane of the same row, so no lane keeps an
+  // old value and none needs to be supplied
+  return __builtin_amdgcn_mov_dpp(v, kCtrl, 0xF, 0xF, true);
 }
 
 template <int kCtrl>
@@ -205,11 +207,15 @@ RQ_DEV void argmax_step(double& v, int& p, int& who) {
 
 // Wave-wide (value, position) maximum with a payload `who`; every lane gets
 // the winner.  Positions of real candidates are distinct, so the winner does
-// not depend on the order in which candidates meet.
-RQ_DEV void wave_argmax(double& v, int& p, int& who) {
-  argmax_step<kDppXor1>(v, p, who);
-  argmax_step<kDppXor2>(v, p, who);
-  argmax_step<kDppHalfMirror>(v, p, who);
+// not depend on the order in which candidates meet.  When every aligned group
+// of G lanes (G = 1, 2, 4 or 8) already holds one candidate, the DPP stages
+// inside a group would compare equal candidates and are left out.
+template <int G>
+RQ_DEV void group_wave_argmax(double& v, int& p, int& who) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 lanes");
+  if (G < 2) argmax_step<kDppXor1>(v, p, who);
+  if (G < 4) argmax_step<kDppXor2>(v, p, who);
+  if (G < 8) argmax_step<kDppHalfMirror>(v, p, who);
   argmax_step<kDppMirror>(v, p, who);
   double bv = readlane_f64(v, 0);
   int bp = __builtin_amdgcn_readlane(p, 0), bw = __builtin_amdgcn_readlane(who, 0);
@@ -226,6 +232,20 @@ RQ_DEV void wave_argmax(double& v, int& p, int& who) {
   v = bv;
   p = bp;
   who = bw;
+}
+
+RQ_DEV void wave_argmax(double& v, int& p, int& who) { group_wave_argmax<1>(v, p, who); }
+
+// The same maximum when only lanes 0..15 hold candidates: the four stages
+// inside the first row of 16 lanes, then lane 0's result to every lane.
+RQ_DEV void row0_argmax(double& v, int& p, int& who) {
+  argmax_step<kDppXor1>(v, p, who);
+  argmax_step<kDppXor2>(v, p, who);
+  argmax_step<kDppHalfMirror>(v, p, who);
+  argmax_step<kDppMirror>(v, p, who);
+  v = readlane_f64(v, 0);
+  p = __builtin_amdgcn_readlane(p, 0);
+  who = __builtin_amdgcn_readlane(who, 0);
 }
 
 typedef double dx4 __attribute__((ext_vector_type(4)));

@@ -3,28 +3,34 @@
 // Each sample column is held in registers by a group of Q lanes (8, or 4 for
 // very wide samples) for the whole kernel: lane q of the group keeps rows q,
 // q+Q, q+2Q, ... (ell <= 96, padded with zero rows), 1024 / Q columns per
-// 1024-thread workgroup.  A pivot step needs
-// the column of largest trailing 2-norm over all workgroups, so every step ends
-// with one cross-workgroup exchange: each workgroup publishes its best
-// (norm^2, position) and that column's values as a record (see the published
-// records in device_common.hpp); once all records are in, every workgroup
-// picks the same winner, forms the same Householder vector from the
-// published column and applies it to its own columns.  Norms of rows j+1.. are
-// recomputed from the transformed columns (no downdating).  Ties go to the
-// lowest current position; positions follow the transpositions j <-> p_j.
-// Work that is the same for the whole workgroup (its record, the winner, the
-// reflector's coefficients) is done by wave 0 alone and shared through LDS: with
+// 1024-thread workgroup.  A pivot step needs the column of largest trailing
+// 2-norm over all workgroups, so every step has one cross-workgroup exchange:
+// each workgroup publishes a record for its best column (see the published
+// records in device_common.hpp) holding (norm^2, position, tau, beta) and the
+// Householder vector that column would define, so that whichever record wins,
+// every workgroup can apply the reflection straight from it.  Norms of rows
+// j+1.. are recomputed from the transformed columns (no downdating).  Ties go
+// to the lowest current position; positions follow the transpositions
+// j <-> p_j.
+//
+// Work that is the same for the whole workgroup (its record, the winner) is
+// done by wave 0 alone while the other waves fetch the records into LDS: with
 // four waves per SIMD, repeating it in every wave would cost four times its
 // latency on every step.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "rqrcp.h"
 
 namespace rq {
 
 constexpr int kSqThreads = 1024;
 constexpr int kSqWaves = kSqThreads / 64;
-constexpr int kSpecCap = 8192;                 // doubles of LDS for the one-round candidate fetch
-constexpr int kPoll = kSpecCap / kSqThreads;   // record words polled per thread
+constexpr int kHead = 4;                        // record head: norm^2, position, tau, beta
+constexpr int kPollers = kSqThreads - 64;       // waves 1.. fetch the records
+constexpr int kPoll = 8;                        // record words one of them polls at most
+constexpr int kSpecCap = kPollers * kPoll;      // record words that fit the one-round fetch
+constexpr int kHeadPer = 4;                     // record heads one lane of wave 0 polls
+static_assert(kHeadPer * 64 >= RQ_MAX_N / 256, "every workgroup's head is polled");
 
 // Sum over the Q lanes holding one column.
 template <int Q>
@@ -32,6 +38,85 @@ RQ_DEV double column_sum(double v) {
   v = quad_sum(v);
   if (Q == 8) v += dpp_f64<kDppHalfMirror>(v);
   return v;
+}
+
+// Waves 1..: wait until the words u, u + kPollers, ... (< total) of a step's
+// records are published, then copy them to s_all.  False when the wait gave up.
+RQ_DEV bool poll_records(const double* rj, int total, const SqArgs& a, int u, double* s_all) {
+  unsigned long long b[kPoll];
+#pragma unroll
+  for (int k = 0; k < kPoll; ++k) {
+    const int e = u + k * kPollers;
+    b[k] = (e < total) ? peek(rj + e) : 0ull;
+  }
+  uint32_t it = 0;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < kPoll; ++k) all = all && b[k] != kUnpublished;
+    if (all) break;
+    if (!keep_waiting(it, a.abort_flag, a.status)) return false;
+#pragma unroll
+    for (int k = 0; k < kPoll; ++k) {
+      const int e = u + k * kPollers;
+      if (e < total && b[k] == kUnpublished) b[k] = peek(rj + e);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPoll; ++k) {
+    const int e = u + k * kPollers;
+    if (e < total) s_all[e] = __longlong_as_double((long long)b[k]);
+  }
+  return true;
+}
+
+// Wave 0: the winner (norm^2 v, position p, workgroup w) over the heads of all
+// records of a step; lane l polls the records l, l + 64, ....  Returns this
+// lane's wait status; the result is wave-uniform.
+RQ_DEV bool poll_winner(const double* rj, const SqArgs& a, int lane, double& v, int& p, int& w) {
+  unsigned long long hv[kHeadPer], hp[kHeadPer];
+#pragma unroll
+  for (int k = 0; k < kHeadPer; ++k) {
+    const int g = lane + 64 * k;
+    hv[k] = (g < a.nwg) ? peek(rj + (int64_t)g * a.rs) : 0ull;
+    hp[k] = (g < a.nwg) ? peek(rj + (int64_t)g * a.rs + 1) : 0ull;
+  }
+  bool ok = true;
+  uint32_t it = 0;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < kHeadPer; ++k) all = all && hv[k] != kUnpublished && hp[k] != kUnpublished;
+    if (all) break;
+    if (!keep_waiting(it, a.abort_flag, a.status)) {
+      ok = false;
+      break;
+    }
+#pragma unroll
+    for (int k = 0; k < kHeadPer; ++k) {
+      const int g = lane + 64 * k;
+      if (g < a.nwg && hv[k] == kUnpublished) hv[k] = peek(rj + (int64_t)g * a.rs);
+      if (g < a.nwg && hp[k] == kUnpublished) hp[k] = peek(rj + (int64_t)g * a.rs + 1);
+    }
+  }
+  v = -1.0;
+  p = INT_MAX;
+  w = 0;
+#pragma unroll
+  for (int k = 0; k < kHeadPer; ++k) {
+    const int g = lane + 64 * k;
+    if (ok && g < a.nwg) {
+      const double vk = __longlong_as_double((long long)hv[k]);
+      const int pk = (int)__longlong_as_double((long long)hp[k]);
+      if (better(vk, pk, v, p)) {
+        v = vk;
+        p = pk;
+        w = g;
+      }
+    }
+  }
+  wave_argmax(v, p, w);
+  return ok;
 }
 
 template <int LM, int Q>
@@ -52,9 +137,8 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   __shared__ double s_wv[kSqWaves];
   __shared__ int s_wp[kSqWaves];
   __shared__ double s_cand[kSqWaves][LM];      // each wave's best column
-  __shared__ double s_all[kSpecCap];
-  __shared__ double s_hh[3];                   // beta, scale, tau of the step's reflector
-  __shared__ int s_hp[2];                      // winner position, its record (-2: timed out)
+  __shared__ double s_all[kSpecCap];           // the step's records
+  __shared__ int s_hp[2];                      // winner position, its record
 
   double x[RPL];
 #pragma unroll
@@ -77,32 +161,22 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
   int pos = own ? c : INT_MAX;
   bool active = own;
   bool flagged = false;
-
-  // Record words this thread polls in every step: all candidates (value,
-  // position) and, when they fit in LDS, their columns.  The offsets within a
-  // step's records are the same for every step.
-  const bool spec = a.nwg * (LM + 2) <= kSpecCap;
-  const int per = spec ? LM + 2 : 2;
-  const int total = a.nwg * per;
-  int off[kPoll];
-#pragma unroll
-  for (int k = 0; k < kPoll; ++k) {
-    const int e = t + k * kSqThreads;
-    const int w = e / per, f = e - w * per;
-    off[k] = (e < total) ? w * a.rs + f : -1;
-  }
+  // All records of a step are fetched into LDS when they fit (one round trip);
+  // otherwise wave 0 fetches the winner's record once it is known.
+  const bool spec = a.nwg * a.rs <= kSpecCap;
 
   for (int j = 0; j < a.steps; ++j) {
     // ---- each wave's best column (its values go to LDS) ---------------------
-    const bool lead = active && q == 0;
-    double bv = lead ? nu2 : -1.0;
-    int bp = lead ? pos : INT_MAX;
+    // All kQ lanes of a column hold bitwise the same norm (see column_sum), so
+    // the wave maximum skips the stages inside a column group.
+    double bv = active ? nu2 : -1.0;
+    int bp = active ? pos : INT_MAX;
     int who = cl;
-    if (lead && !flagged && !(nu2 <= 1.7976931348623157e308)) {
+    if (active && q == 0 && !flagged && !(nu2 <= 1.7976931348623157e308)) {
       raise_status(a.status, kErrNonFinite);
       flagged = true;
     }
-    wave_argmax(bv, bp, who);
+    group_wave_argmax<kQ>(bv, bp, who);
     if (bp != INT_MAX && cl == who) {
 #pragma unroll
       for (int i = 0; i < RPL; ++i) s_cand[wave][q + kQ * i] = x[i];
@@ -112,113 +186,67 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       s_wp[wave] = bp;
     }
     __syncthreads();
-    // ---- wave 0 publishes the workgroup's record; the other waves go straight
-    // to polling (one wave doing this keeps the SIMDs free of repeated work)
+    const double* rj = a.rec + (int64_t)j * a.nwg * a.rs;
+    bool ok = true;
     if (wave == 0) {
+      // ---- the workgroup's best column and its reflector, published --------
       double v = (lane < kSqWaves) ? s_wv[lane] : -1.0;
       int p = (lane < kSqWaves) ? s_wp[lane] : INT_MAX;
       int w = lane;
-      wave_argmax(v, p, w);
+      row0_argmax(v, p, w);
       double* rec = a.rec + ((int64_t)j * a.nwg + wg) * a.rs;
+      double beta = 0.0, scale = 0.0, tau = 0.0;
       if (p != INT_MAX) {
-        for (int r = lane; r < LM; r += 64) publish(rec + 2 + r, s_cand[w][r]);
+        // v is the sum of squares of the column's rows j.., the s2 of its reflector
+        if (v > 0.0) reflector_coeffs(s_cand[w][j], v, beta, scale, tau);
+        for (int r = lane; r < LM; r += 64)
+          publish(rec + kHead + r, (r < j) ? 0.0 : (r == j ? 1.0 : s_cand[w][r] * scale));
       } else {
-        for (int r = lane; r < LM; r += 64) publish(rec + 2 + r, 0.0);
+        for (int r = lane; r < LM; r += 64) publish(rec + kHead + r, 0.0);
       }
       if (lane == 0) {
+        publish(rec + 2, tau);
+        publish(rec + 3, beta);
         publish(rec, v);
         publish(rec + 1, (double)p);
       }
-    }
-    // ---- exchange: wait for every workgroup's record of this step -------------
-    const double* rj = a.rec + (int64_t)j * a.nwg * a.rs;
-    bool ok = true;
-    {
-      unsigned long long b[kPoll];
-#pragma unroll
-      for (int k = 0; k < kPoll; ++k) b[k] = (off[k] >= 0) ? peek(rj + off[k]) : 0ull;
-      uint32_t it = 0;
-      while (true) {
-        bool all = true;
-#pragma unroll
-        for (int k = 0; k < kPoll; ++k) all = all && b[k] != kUnpublished;
-        if (all) break;
-        if (!keep_waiting(it, a.abort_flag, a.status)) {
-          ok = false;
-          break;
-        }
-#pragma unroll
-        for (int k = 0; k < kPoll; ++k)
-          if (off[k] >= 0 && b[k] == kUnpublished) b[k] = peek(rj + off[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < kPoll; ++k) {
-        const int e = t + k * kSqThreads;
-        if (e < total) s_all[e] = __longlong_as_double((long long)b[k]);
-      }
-    }
-    if (__syncthreads_or(!ok)) return;
-    // ---- wave 0 finds the winner and forms its reflector; the others wait -----
-    if (wave == 0) {
-      double v = -1.0;
-      int p = INT_MAX, w = 0;
-      for (int i = lane; i < a.nwg; i += 64) {
-        const double vi = s_all[i * per];
-        const int pi = (int)s_all[i * per + 1];
-        if (better(vi, pi, v, p)) {
-          v = vi;
-          p = pi;
-          w = i;
-        }
-      }
-      wave_argmax(v, p, w);
-      bool okc = true;
-      if (p != INT_MAX && !spec) {
-        // columns did not fit: fetch the winner's column into the front of s_all
-        for (int r = lane; r < LM && okc; r += 64) {
-          const double* src = rj + (int64_t)w * a.rs + 2 + r;
+      // ---- the winner over all workgroups, from the record heads ----------
+      double wv;
+      int wp, ww;
+      ok = poll_winner(rj, a, lane, wv, wp, ww);
+      if (__builtin_amdgcn_ballot_w64(!ok) == 0 && wp != INT_MAX && !spec) {
+        // the records did not fit in LDS: fetch the winner's record
+        for (int r = lane; r < a.rs && ok; r += 64) {
+          const double* src = rj + (int64_t)ww * a.rs + r;
           unsigned long long bt = peek(src);
           uint32_t it = 0;
           while (bt == kUnpublished) {
             if (!keep_waiting(it, a.abort_flag, a.status)) {
-              okc = false;
+              ok = false;
               break;
             }
             bt = peek(src);
           }
-          s_all[2 + r] = __longlong_as_double((long long)bt);
+          s_all[r] = __longlong_as_double((long long)bt);
         }
-        w = 0;
-        // lane 0 reads words other lanes of this wave wrote
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ww = 0;
       }
-      const bool wave_ok = __builtin_amdgcn_ballot_w64(!okc) == 0;
       if (lane == 0) {
-        s_hp[0] = p;
-        s_hp[1] = wave_ok ? w : -2;
-        if (p != INT_MAX && wave_ok) {
-          // the winner's value is the sum of squares of its rows j.., exactly
-          // the s2 its reflector needs
-          const double alpha = s_all[(spec ? w * (LM + 2) : 0) + 2 + j];
-          double beta = 0.0, tau = 0.0, scale = 0.0;
-          if (v > 0.0) reflector_coeffs(alpha, v, beta, scale, tau);
-          s_hh[0] = beta;
-          s_hh[1] = scale;
-          s_hh[2] = tau;
-        }
+        s_hp[0] = wp;
+        s_hp[1] = ww;
       }
+    } else if (spec) {
+      ok = poll_records(rj, a.nwg * a.rs, a, t - 64, s_all);
     }
-    __syncthreads();
-    const int wpos = s_hp[0], wwg = s_hp[1];
+    if (__syncthreads_or(!ok)) return;
+    const int wpos = s_hp[0];
     if (wpos == INT_MAX) {          // every workgroup sees the same: consistent exit
       if (t == 0 && wg == 0) raise_status(a.status, kErrNoPivot);
       return;
     }
-    if (wwg < 0) return;            // the winner's column never arrived (status raised)
-    const double beta = s_hh[0], scale = s_hh[1], tau = s_hh[2];
-    const double* col = s_all + (spec ? wwg * (LM + 2) : 0) + 2;   // winner's column in LDS
+    const double* hrec = s_all + (spec ? s_hp[1] * a.rs : 0);   // winner's record
+    const double tau = hrec[2], beta = hrec[3];
+    const double* vh = hrec + kHead;                            // its Householder vector
     // ---- positions: j <-> wpos ----------------------------------------------
     if (active) {
       if (pos == wpos) {
@@ -234,37 +262,36 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
       }
     }
     // ---- apply the reflection to the remaining columns ---------------------------
-    // The Householder vector is formed on the fly from the winner's column in LDS
-    // (every lane of a column group reads the same words: broadcast reads).
     if (active) {
-      double v[RPL];
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const int r = q + kQ * i;
-        v[i] = (r < j) ? 0.0 : (r == j ? 1.0 : col[r] * scale);
+        const double vi = vh[q + kQ * i];
         if (i & 1)
-          d1 += v[i] * x[i];
+          d1 += vi * x[i];
         else
-          d0 += v[i] * x[i];
+          d0 += vi * x[i];
       }
       const double d = tau * column_sum<kQ>(d0 + d1);
+      // the vector is read from LDS again rather than held in registers across
+      // the reduction (the empty asm keeps the compiler from reusing the reads)
+      asm volatile("" ::: "memory");
       double n0 = 0.0, n1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        x[i] -= d * v[i];
-        const double sq = (q + kQ * i > j) ? x[i] * x[i] : 0.0;
+        x[i] -= d * vh[q + kQ * i];
+        const double xm = (q + kQ * i > j) ? x[i] : 0.0;
         if (i & 1)
-          n1 += sq;
+          n1 = fma(xm, xm, n1);
         else
-          n0 += sq;
+          n0 = fma(xm, xm, n0);
       }
       nu2 = column_sum<kQ>(n0 + n1);
     }
     // No barrier here: the next step rewrites s_wv, s_wp and s_cand only after
-    // this step's barriers (wave 0 read them before the first), s_all only
+    // this step's second barrier (wave 0 read them before it), s_all only
     // after its own first barrier (which follows this step's last read of
-    // s_all), and s_hh, s_hp only after its own poll barrier.
+    // s_all), and s_hp before its own second barrier.
   }
   // Every workgroup loaded its columns before the first barrier, so the
   // in-place write of the permuted sample cannot overwrite unread input.
@@ -287,7 +314,9 @@ int sq_lm(int ell) {
   return ((ell + 7) / 8) * 8;
 }
 
-int sq_record_stride(int lm) { return ((lm + 2 + 7) / 8) * 8; }
+// Records are packed (no padding) so that a step's records are polled as one
+// contiguous run of words.
+int sq_record_stride(int lm) { return lm + kHead; }
 
 // Every workgroup of the persistent kernel must be resident at once, so the
 // wider layout (8 lanes per column, twice the workgroups) is used only within
