@@ -9,6 +9,13 @@ factors its own pre-staged copy of A, so nothing but the factorization runs in
 the timed region.  The throughput counts the nominal 4n^3/3 flops of a full
 Householder QR (the same count used for plain QRCP and unpivoted QR).
 
+Before the timed steps, one step runs with every kernel bracketed by HIP events:
+its per-kernel times are the reported breakdown (`kernels_ms_per_step`, with the
+wall time of that step as `profiled_ms_per_step`) and its longest kernel class
+is the one the roofline covers.  The timed steps bracket only that class with
+events (two per launch), since events around every launch add device time of
+their own; the plain QRCP comparator is timed with no events at all.
+
 Prints progress on stderr and one JSON line on stdout.
 """
 from __future__ import annotations
@@ -50,6 +57,49 @@ def profile_table(h):
             out[name.value.decode()] = dict(launches=launches.value, ms=ms.value, flops=fl.value,
                                             bytes=by.value)
     return out
+
+
+ALL_CLASSES = 0xFFFFFFFF
+
+
+def class_mask(h, names):
+    """Bit mask of the library's kernel classes with the given names."""
+    from paper_2008_04447_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    mask = 0
+    for i in range(lib.rq_profile_count(h.ptr)):
+        name = ctypes.c_char_p()
+        launches = ctypes.c_int64()
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib.rq_profile_get(h.ptr, i, ctypes.byref(name), ctypes.byref(launches), ctypes.byref(ms),
+                           ctypes.byref(fl), ctypes.byref(by))
+        if name.value.decode() in names:
+            mask |= 1 << i
+    return mask
+
+
+def profiled_step(fn, h):
+    """One call of fn with every kernel bracketed by HIP events: the per-kernel
+    breakdown and the call's wall time in ms (the events add device time of
+    their own, so this time is not the throughput measurement)."""
+    import torch
+    from paper_2008_04447_amd import _lib
+    lib = _lib.load()
+    lib.rq_profile_classes(h.ptr, ALL_CLASSES)
+    lib.rq_profile_start(h.ptr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.rq_profile_stop(h.ptr)
+    h.sync()
+    return (t1 - t0) * 1e3, profile_table(h), out
+
+
+def dominant(breakdown):
+    return max(breakdown.items(), key=lambda kv: kv[1]["ms"])[0] if breakdown else None
 
 
 PROFILE = os.path.join(ROOT, "profiles", "rqrcp_fp64_8000_kernels.txt")
@@ -137,7 +187,8 @@ def bench_rqrcp(args):
     om = synth.omega(ell, m, synth.seed_for(1, "Omega"))
     A0 = api.colmajor(a, device=dev)
     Om = api.colmajor(om, device=dev)
-    copies = [A0.clone(memory_format=torch.preserve_format) for _ in range(args.warmup + args.steps)]
+    copies = [A0.clone(memory_format=torch.preserve_format)
+              for _ in range(args.warmup + 1 + args.steps)]
     for c in copies:
         assert c.stride(0) == 1
     h = api.default_handle(0)
@@ -147,15 +198,24 @@ def bench_rqrcp(args):
         api.rqrcp_factor(copies[i], Om, b, p, handle=h)
         h.sync()
     lib = _lib.load()
+    # one step with every kernel timed: the per-kernel breakdown and the dominant kernel
+    pms, breakdown, _ = profiled_step(lambda: api.rqrcp_factor(copies[args.warmup], Om, b, p,
+                                                               handle=h), h)
+    dom = dominant(breakdown)
+    log(f"profiled step {pms:.2f} ms (every kernel bracketed by events); dominant kernel {dom}")
+    # the timed steps: events only around the dominant kernel (its launch durations
+    # give the roofline), none around the others
+    lib.rq_profile_classes(h.ptr, class_mask(h, [dom]))
     lib.rq_profile_start(h.ptr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outs = []
     for i in range(args.steps):
-        outs.append(api.rqrcp_factor(copies[args.warmup + i], Om, b, p, handle=h))
+        outs.append(api.rqrcp_factor(copies[args.warmup + 1 + i], Om, b, p, handle=h))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lib.rq_profile_stop(h.ptr)
+    lib.rq_profile_classes(h.ptr, ALL_CLASSES)
     h.sync()
     ms = (t1 - t0) * 1e3 / args.steps
     prof = profile_table(h)
@@ -177,25 +237,26 @@ def bench_rqrcp(args):
     if not args.no_plain:
         # plain QRCP (Algorithm 2) on the same matrix, same device: the comparator
         qsteps = max(1, min(args.steps, 2))
-        qcopies = [A0.clone(memory_format=torch.preserve_format) for _ in range(qsteps + 1)]
-        log(f"plain QRCP: 1 warmup + {qsteps} timed step(s)")
+        qcopies = [A0.clone(memory_format=torch.preserve_format) for _ in range(qsteps + 2)]
+        log(f"plain QRCP: 1 warmup + 1 profiled + {qsteps} timed step(s)")
         api.qrcp_factor(qcopies[0], nb=32, handle=h)
         h.sync()
-        lib.rq_profile_start(h.ptr)
+        qpms, qprof, _ = profiled_step(lambda: api.qrcp_factor(qcopies[1], nb=32, handle=h), h)
+        lib.rq_profile_classes(h.ptr, 0)
         torch.cuda.synchronize()
         tq0 = time.perf_counter()
         for i in range(qsteps):
-            qj, _ = api.qrcp_factor(qcopies[1 + i], nb=32, handle=h)
+            qj, _ = api.qrcp_factor(qcopies[2 + i], nb=32, handle=h)
         torch.cuda.synchronize()
         tq1 = time.perf_counter()
-        lib.rq_profile_stop(h.ptr)
+        lib.rq_profile_classes(h.ptr, ALL_CLASSES)
         h.sync()
         qms = (tq1 - tq0) * 1e3 / qsteps
-        qprof = profile_table(h)
         plain = {"ms_per_step": round(qms, 3), "value": round(flops / (qms * 1e-3) / 1e12, 4),
                  "unit": "TFLOP/s", "nb": 32, "steps": qsteps,
                  "rqrcp_speedup": round(qms / ms, 3),
-                 "kernels_ms_per_step": {k: round(v["ms"] / qsteps, 3) for k, v in qprof.items()}}
+                 "profiled_ms_per_step": round(qpms, 3),
+                 "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in qprof.items()}}
         log(f"plain QRCP {qms:.2f} ms/step -> RQRCP speedup {qms / ms:.2f}x")
         del qcopies
 
@@ -218,7 +279,8 @@ def bench_rqrcp(args):
                    "p": p},
         "roofline": roof,
         "first_block_pivots_match_oracle": ok,
-        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
+        "profiled_ms_per_step": round(pms, 3),
+        "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in breakdown.items()},
         "plain_qrcp": plain,
     }
     if not args.no_cpu:
@@ -253,12 +315,18 @@ def _gpu_mem_clear():
 
 
 def _timed(fn, steps, warmup, h):
+    """Warm-up calls, one profiled call (per-kernel breakdown), then `steps`
+    timed calls with events only around the dominant kernel.  Returns ms per
+    timed call, the last output, the dominant kernel's timings and the
+    breakdown."""
     import torch
     from paper_2008_04447_amd import _lib
     lib = _lib.load()
     for _ in range(warmup):
         fn()
         h.sync()
+    _, breakdown, _ = profiled_step(fn, h)
+    lib.rq_profile_classes(h.ptr, class_mask(h, [dominant(breakdown)]))
     lib.rq_profile_start(h.ptr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -268,8 +336,9 @@ def _timed(fn, steps, warmup, h):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lib.rq_profile_stop(h.ptr)
+    lib.rq_profile_classes(h.ptr, ALL_CLASSES)
     h.sync()
-    return (t1 - t0) * 1e3 / steps, out, profile_table(h)
+    return (t1 - t0) * 1e3 / steps, out, profile_table(h), breakdown
 
 
 def bench_trqrcp_c3(args):
@@ -292,8 +361,9 @@ def bench_trqrcp_c3(args):
     A64.copy_(A32)                              # the FP64 run sees the same FP32 values
     om = api.colmajor(synth.omega(b + p, m, synth.seed_for(2, "Omega")), device=dev)
     h = api.default_handle(0)
-    ms, out, prof = _timed(lambda: api.trqrcp_truncate(A32, om, b, p, k, handle=h), args.c3_steps, 1, h)
-    ms64, out64, _ = _timed(lambda: api.trqrcp_truncate(A64, om, b, p, k, handle=h), 1, 1, h)
+    ms, out, prof, brk = _timed(lambda: api.trqrcp_truncate(A32, om, b, p, k, handle=h),
+                                args.c3_steps, 1, h)
+    ms64, out64, _, _ = _timed(lambda: api.trqrcp_truncate(A64, om, b, p, k, handle=h), 1, 1, h)
 
     def err(o):
         jp, Y, T, R = o
@@ -309,7 +379,7 @@ def bench_trqrcp_c3(args):
            "dtype": "bf16-mfma/fp32-acc, fp64 panel", "fp64_ms_per_step": round(ms64, 3),
            "trunc_error": e32, "trunc_error_fp64": e64, "error_ratio": round(e32 / e64, 5),
            "optimal_svd_error": opt, "flops_per_step": fl, "roofline": roof,
-           "kernels_ms_per_step": {kk: round(v["ms"] / args.c3_steps, 3) for kk, v in prof.items()},
+           "kernels_ms_per_step": {kk: round(v["ms"], 3) for kk, v in brk.items()},
            "config": {"workload": "trqrcp_mixed_20000x20000_exp200", "m": m, "n": n, "k": k, "b": b,
                       "p": p}}
     log(f"C3: {ms:.2f} ms/step ({res['value']} TFLOP/s), error {e32:.5e} vs fp64 {e64:.5e} "
@@ -337,8 +407,9 @@ def bench_tuxv_c4(args):
     A64.copy_(A32)
     om = api.colmajor(synth.omega(b + p, m, synth.seed_for(3, "Omega")), device=dev)
     h = api.default_handle(0)
-    ms, out, prof = _timed(lambda: api.tuxv_svd(A32, om, b, p, k, handle=h), args.c4_steps, 1, h)
-    ms64, out64, _ = _timed(lambda: api.tuxv_svd(A64, om, b, p, k, handle=h), 1, 1, h)
+    ms, out, prof, brk = _timed(lambda: api.tuxv_svd(A32, om, b, p, k, handle=h), args.c4_steps,
+                                1, h)
+    ms64, out64, _, _ = _timed(lambda: api.tuxv_svd(A64, om, b, p, k, handle=h), 1, 1, h)
 
     def err(o):
         U, X, V, _ = o
@@ -355,7 +426,7 @@ def bench_tuxv_c4(args):
            "sigma_rel_err_median": float(np.median(rel)), "sigma_rel_err_max": float(rel.max()),
            "sigma_rel_err_median_top64": float(np.median(rel[:64])),
            "flops_per_step": fl, "roofline": roof,
-           "kernels_ms_per_step": {kk: round(v["ms"] / args.c4_steps, 3) for kk, v in prof.items()},
+           "kernels_ms_per_step": {kk: round(v["ms"], 3) for kk, v in brk.items()},
            "config": {"workload": "tuxv_mixed_50000x8000_poly1.5_noise1e-6", "m": m, "n": n, "k": k,
                       "b": b, "p": p}}
     log(f"C4: {ms:.2f} ms/step ({res['value']} TFLOP/s), error ratio {e32 / e64:.4f}, "

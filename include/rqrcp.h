@@ -207,13 +207,18 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
 
 /*
  * Kernel timing for measurement.  Between rq_profile_start and rq_profile_stop
- * every kernel the handle launches is bracketed by HIP events on the handle's
- * stream and attributed to a named kernel class together with its algorithmic
+ * every kernel the handle launches is bracketed by HIP events on the stream it
+ * runs on and attributed to a named kernel class together with its algorithmic
  * flop and byte counts (the work the mathematics needs, not what the hardware
  * moved).  rq_profile_stop waits for the stream and folds the events into
  * per-class totals, which rq_profile_get reports (class index 0..count-1).
+ * rq_profile_classes restricts the timing to the classes whose bit
+ * (1u << index) is set in mask (all classes until it is called): each timed
+ * launch records two events, a few microseconds of device time, so a run that
+ * measures throughput times only the classes it reports.
  * Errors: -1 null handle, -2 index out of range.
  */
+rq_status rq_profile_classes(rq_handle h, uint32_t mask);
 rq_status rq_profile_start(rq_handle h);
 rq_status rq_profile_stop(rq_handle h);
 int32_t rq_profile_count(rq_handle h);

@@ -40,7 +40,7 @@ static hipEvent_t next_event(rq_handle h) {
 
 KTimer::KTimer(rq_handle h_, int cls_, double f_, double b_, hipStream_t s_)
     : h(h_), cls(cls_), f(f_), b(b_), s(s_) {
-  if (h->prof) {
+  if (h->prof && ((h->prof_mask >> cls) & 1u)) {
     e0 = next_event(h);
     if (e0) (void)hipEventRecord(e0, s);
   }
@@ -165,7 +165,7 @@ size_t sq_rec_doubles(int ell, int64_t N) {
 }
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
-                          SqWork w, int64_t* perm) {
+                          SqWork w, int64_t* perm, hipEvent_t queued) {
   const int lm = sq_lm(ell);
   SqArgs a{};
   a.B = B;
@@ -184,6 +184,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.perm = perm;
   RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
   KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
+  if (queued) RQ_CHECK(h, hipEventRecord(queued, h->stream));
   RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
   return RQ_OK;
 }
@@ -316,6 +317,12 @@ rq_status rq_sync_status(rq_handle h, int64_t* device_error) {
   if (st[0]) RQ_CHECK(h, hipMemset(h->status, 0, 4 * sizeof(int64_t)));
   if (device_error) *device_error = st[0];
   return st[0] ? RQ_E_DEVICE : RQ_OK;
+}
+
+rq_status rq_profile_classes(rq_handle h, uint32_t mask) {
+  if (!h) return -1;
+  h->prof_mask = mask;
+  return RQ_OK;
 }
 
 rq_status rq_profile_start(rq_handle h) {
@@ -477,7 +484,33 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_z, hipEventDisableTiming));
     RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_u, hipEventDisableTiming));
   }
-  bool pending_rows = false;
+  // The update of the rows below R12 runs on the side stream.  It is handed to
+  // that stream only after the next block's sample QRCP is queued and waits on
+  // an event recorded right before that launch: the persistent kernel needs
+  // whole compute units, and reaching the dispatcher first it gets them before
+  // the update's many workgroups fill the device.
+  struct SideUpdate {
+    double* C;
+    int64_t M, N;
+    const double* Y;
+    int bj;
+  } side{};
+  bool side_queued = false;   // `side` is waiting to be handed to the side stream
+  bool pending_rows = false;  // the side stream holds an update the main stream must wait for
+  auto release_side = [&]() -> rq_status {
+    RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_z, 0));
+    {
+      const double Mr = (double)side.M, Nr = (double)side.N;
+      KTimer kt(h, K_UPDATE, 2.0 * side.bj * Mr * Nr,
+                8.0 * (2.0 * Mr * Nr + Mr * side.bj + (double)side.bj * Nr), h->side);
+      RQ_CHECK(h, launch_update(side.C, lda, (int)side.M, (int)side.N, side.Y, m, zbuf, 64,
+                                side.bj, h->side));
+    }
+    RQ_CHECK(h, hipEventRecord(h->ev_u, h->side));
+    side_queued = false;
+    pending_rows = true;
+    return RQ_OK;
+  };
 
   // ---- B = Omega A -------------------------------------------------------------
   RQ_TRY(sketch_fp64(h, (int)ell, m, n, Omega, ldo, A, lda, sample, ell, part));
@@ -489,7 +522,9 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     const int64_t M = m - col0;
     double* Ablk = A + col0 + col0 * lda;            // trailing block A(col0:, col0:)
     // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
-    RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr));
+    RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr,
+                           side_queued ? h->ev_z : nullptr));
+    if (side_queued) RQ_TRY(release_side());
     // the previous block's update of rows below its R12 must be complete
     if (pending_rows) {
       RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
@@ -540,12 +575,11 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_CHECK(h, launch_reduce(part, 64, g.split_stride, ks, bj, (int)Nt, zbuf, 64, tblk, 64,
                                 bj, s));
     }
-    // 5. A_trailing -= Y Z.  Rows 0..bj-1 (R12) are updated first on the main
-    // stream: the sample update and the next block's sample QRCP need only them.
-    // The other rows are updated on the side stream, started only after the
-    // sample update so that the short kernels on the main stream run without
-    // contention; the next block waits for them before it permutes and factors
-    // its panel.
+    // 5. A_trailing -= Y Z.  Rows 0..bj-1 (R12) are updated on the main stream:
+    // the sample update and the next block's sample QRCP need only them.  The
+    // other rows go to the side stream alongside the next sample QRCP (see
+    // release_side); the next block waits for them before it permutes and
+    // factors its panel.
     {
       KTimer kt(h, K_UPDATE, 2.0 * bj * (double)bj * Nt,
                 8.0 * (2.0 * bj * Nt + (double)bj * bj + (double)bj * Nt));
@@ -556,18 +590,13 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
                                mhat));
     if (M > bj) {
-      RQ_CHECK(h, hipEventRecord(h->ev_z, s));
-      RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_z, 0));
-      {
-        const double Mr = (double)(M - bj);
-        KTimer kt(h, K_UPDATE, 2.0 * bj * Mr * Nt, 8.0 * (2.0 * Mr * Nt + Mr * bj + (double)bj * Nt),
-                  h->side);
-        RQ_CHECK(h, launch_update(Ctr + bj, lda, (int)(M - bj), (int)Nt, ybuf + bj, m, zbuf, 64, bj,
-                                  h->side));
-      }
-      RQ_CHECK(h, hipEventRecord(h->ev_u, h->side));
-      pending_rows = true;
+      side = SideUpdate{Ctr + bj, M - bj, Nt, ybuf + bj, bj};
+      side_queued = true;
     }
+  }
+  if (side_queued) {                // no sample QRCP follows: release it now
+    RQ_CHECK(h, hipEventRecord(h->ev_z, s));
+    RQ_TRY(release_side());
   }
   if (pending_rows) RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
   return RQ_OK;

@@ -64,6 +64,7 @@ struct rq_handle_s {
   hipEvent_t ev_z = nullptr, ev_u = nullptr;
   std::string last_error;
   bool prof = false;
+  uint32_t prof_mask = ~0u;     // kernel classes timed while prof is set
   std::vector<rq::ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
@@ -152,8 +153,10 @@ rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, 
 // doubles of workspace that hold the BF16 staging of an operand with K columns
 inline size_t bf16_stage_doubles(int64_t K) { return (size_t)(bf16_stage_elems(K) + 3) / 4; }
 size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
+// `queued`, when given, is recorded on the handle's stream right before the
+// kernel launch (work that waits on it becomes ready together with the launch).
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
-                          SqWork w, int64_t* perm);
+                          SqWork w, int64_t* perm, hipEvent_t queued = nullptr);
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt);
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
