@@ -267,6 +267,10 @@ rq_status rq_create(rq_handle* out, int device, void* hip_stream) {
   rq_handle h = new rq_handle_s();
   h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    h->update_wgs = cus;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->status), 4 * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->sync), 64 * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->status, 0, 4 * sizeof(int64_t), h->stream);
@@ -497,14 +501,15 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   } side{};
   bool side_queued = false;   // `side` is waiting to be handed to the side stream
   bool pending_rows = false;  // the side stream holds an update the main stream must wait for
-  auto release_side = [&]() -> rq_status {
+  // `beside`: workgroups of the sample QRCP the update runs next to
+  auto release_side = [&](int beside) -> rq_status {
     RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_z, 0));
     {
       const double Mr = (double)side.M, Nr = (double)side.N;
       KTimer kt(h, K_UPDATE, 2.0 * side.bj * Mr * Nr,
                 8.0 * (2.0 * Mr * Nr + Mr * side.bj + (double)side.bj * Nr), h->side);
       RQ_CHECK(h, launch_update(side.C, lda, (int)side.M, (int)side.N, side.Y, m, zbuf, 64,
-                                side.bj, h->side));
+                                side.bj, std::max(1, h->update_wgs - beside), h->side));
     }
     RQ_CHECK(h, hipEventRecord(h->ev_u, h->side));
     side_queued = false;
@@ -524,7 +529,7 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
     RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr,
                            side_queued ? h->ev_z : nullptr));
-    if (side_queued) RQ_TRY(release_side());
+    if (side_queued) RQ_TRY(release_side(sq_groups(N, h->max_groups)));
     // the previous block's update of rows below its R12 must be complete
     if (pending_rows) {
       RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
@@ -583,7 +588,7 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     {
       KTimer kt(h, K_UPDATE, 2.0 * bj * (double)bj * Nt,
                 8.0 * (2.0 * bj * Nt + (double)bj * bj + (double)bj * Nt));
-      RQ_CHECK(h, launch_update(Ctr, lda, bj, (int)Nt, ybuf, m, zbuf, 64, bj, s));
+      RQ_CHECK(h, launch_update(Ctr, lda, bj, (int)Nt, ybuf, m, zbuf, 64, bj, h->update_wgs, s));
     }
     // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
     if (col0 + bj < k)
@@ -596,7 +601,7 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   }
   if (side_queued) {                // no sample QRCP follows: release it now
     RQ_CHECK(h, hipEventRecord(h->ev_z, s));
-    RQ_TRY(release_side());
+    RQ_TRY(release_side(0));
   }
   if (pending_rows) RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
   return RQ_OK;

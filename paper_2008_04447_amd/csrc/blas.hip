@@ -8,6 +8,8 @@
 #include "device_common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace rq {
 
 // ---------------------------------------------------------------------------
@@ -394,9 +396,123 @@ hipError_t launch_gemm_nn(double* C, int64_t ldc, int M, int N, const double* Y,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Trailing update of tall blocks, C(M x N) -= Y(M x K) Z(K x N) with K <= 64
+// (the rank-b update of Algorithm 4).  A 1024-thread workgroup owns 256 rows
+// (wave w: 16 rows, whose Y operands it keeps in registers for the whole
+// launch) and walks the 64-column blocks cg, cg + G, cg + 2G, ...: each block's
+// Z (64 x 64, negated) is staged once in LDS for all 16 waves, double-buffered,
+// and the next block's C and Z are fetched while the current one is on the
+// matrix cores.  C is read and written exactly once.  Each workgroup fills one
+// compute unit, so the grid (row groups x G) is sized to the units the launch
+// may take.
+constexpr int kStripRows = 256;
+constexpr int kZld = 72;   // LDS row stride of a staged Z block [k][col] (2-way banked reads)
+
+__global__ __launch_bounds__(1024) void update_strip_kernel(double* C, int64_t ldc, int M, int N,
+                                                            const double* Y, int64_t ldy,
+                                                            const double* Z, int64_t ldz, int K,
+                                                            int G) {
+  __shared__ double sZ[2][64 * kZld];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int rg = blockIdx.x / G, cg = blockIdx.x - rg * G;
+  const int row = rg * kStripRows + wave * 16 + l16;
+  const bool rok = row < M;
+  const int nblk = (N + 63) / 64;
+  if (cg >= nblk) return;                       // the whole workgroup
+  // B operands of the 16 k-steps: Y(row, 4 s + kq)
+  double yv[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k = 4 * s + kq;
+    yv[s] = (rok && k < K) ? Y[row + (int64_t)k * ldy] : 0.0;
+  }
+  // thread t stages Z rows zk..zk+3 of the block's column zc
+  const int zc = t >> 4, zk = (t & 15) * 4;
+  double zs[4];
+  auto fetch_z = [&](int cb) {
+    const int col = cb * 64 + zc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      zs[i] = (col < N && zk + i < K) ? Z[(zk + i) + (int64_t)col * ldz] : 0.0;
+  };
+  auto put_z = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sZ[b][(zk + i) * kZld + zc] = -zs[i];
+  };
+  // accumulator layout of the 16 x 16 blocks jb: lane holds column
+  // 16 jb + kq + 4 i of the block, row `row`
+  auto fetch_c = [&](int cb, dx4(&v)[4]) {
+    const double* cp = C + row + (int64_t)(cb * 64 + kq) * ldc;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int col = cb * 64 + 16 * jb + kq + 4 * i;
+        v[jb][i] = (rok && col < N) ? cp[(int64_t)(16 * jb + 4 * i) * ldc] : 0.0;
+      }
+  };
+  auto compute_store = [&](int cb, int b, dx4(&acc)[4]) {
+    const double* zb = sZ[b];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 4 * s + kq;
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) acc[jb] = mfma_f64(zb[k * kZld + 16 * jb + l16], yv[s], acc[jb]);
+    }
+    double* cp = C + row + (int64_t)(cb * 64 + kq) * ldc;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int col = cb * 64 + 16 * jb + kq + 4 * i;
+        if (rok && col < N) cp[(int64_t)(16 * jb + 4 * i) * ldc] = acc[jb][i];
+      }
+  };
+  // two named accumulator sets alternate (the walk is unrolled by two), so the
+  // prefetched block never has to be copied
+  dx4 accA[4], accB[4];
+  int cb = cg;
+  fetch_z(cb);
+  fetch_c(cb, accA);
+  put_z(0);
+  __syncthreads();
+  while (true) {
+    int cn = cb + G;
+    if (cn < nblk) {
+      fetch_z(cn);
+      fetch_c(cn, accB);
+    }
+    compute_store(cb, 0, accA);
+    if (cn >= nblk) break;
+    put_z(1);
+    __syncthreads();   // buffer 1 complete; every wave is done with buffer 0
+    cb = cn;
+    cn = cb + G;
+    if (cn < nblk) {
+      fetch_z(cn);
+      fetch_c(cn, accA);
+    }
+    compute_store(cb, 1, accB);
+    if (cn >= nblk) break;
+    put_z(0);
+    __syncthreads();
+    cb = cn;
+  }
+}
+
 hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
-                         const double* Z, int64_t ldz, int bj, hipStream_t s) {
-  return launch_gemm_nn(C, ldc, M, N, Y, ldy, Z, ldz, bj, -1.0, 1.0, s);
+                         const double* Z, int64_t ldz, int bj, int max_wgs, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (bj < 1 || bj > 64) return hipErrorInvalidValue;
+  if (M < kStripRows || max_wgs < 1)
+    return launch_gemm_nn(C, ldc, M, N, Y, ldy, Z, ldz, bj, -1.0, 1.0, s);
+  const int nrg = (M + kStripRows - 1) / kStripRows, nblk = (N + 63) / 64;
+  const int G = std::max(1, std::min(nblk, max_wgs / nrg));
+  hipLaunchKernelGGL(update_strip_kernel, dim3(nrg * G), dim3(1024), 0, s, C, ldc, M, N, Y, ldy, Z,
+                     ldz, bj, G);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

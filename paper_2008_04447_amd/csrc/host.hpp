@@ -60,6 +60,7 @@ struct rq_handle_s {
   int64_t* status = nullptr;   // device int64[4]
   uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag
   int max_groups = 128;        // workgroups one persistent sample-QRCP launch may use
+  int update_wgs = 256;        // compute units a trailing-update launch may fill (device count)
   hipStream_t side = nullptr;  // second stream of the RQRCP block loop (created on first use)
   hipEvent_t ev_z = nullptr, ev_u = nullptr;
   std::string last_error;

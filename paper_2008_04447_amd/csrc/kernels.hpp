@@ -94,9 +94,11 @@ hipError_t launch_reduce_t(const double* part, int64_t ldp, int64_t sstride, int
                            double* Z, int64_t ldz, bool zero_pad, const double* T, int64_t ldt,
                            int bj, bool trans, hipStream_t s);
 
-// C(M x N) -= Y(M x K) Z(K x N) with K = bj (Y, Z read only for k < K).
+// C(M x N) -= Y(M x K) Z(K x N) with K = bj <= 64 (Y, Z read only for k < K).
+// Tall blocks use workgroups that each fill a compute unit; at most max_wgs of
+// them (the units the launch may take beside concurrent persistent kernels).
 hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
-                         const double* Z, int64_t ldz, int bj, hipStream_t s);
+                         const double* Z, int64_t ldz, int bj, int max_wgs, hipStream_t s);
 // C(M x N) = beta C + alpha Y(M x K) Z(K x N), any K (FP64 MFMA, 64 x 64 tiles).
 hipError_t launch_gemm_nn(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
                           const double* Z, int64_t ldz, int K, double alpha, double beta,

@@ -379,7 +379,7 @@ extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, i
         KTimer kt(h, K_UPDATE, 2.0 * kb * (double)(m - j1) * (n - j1),
                   8.0 * (2.0 * (m - j1) * (double)(n - j1)));
         RQ_CHECK(h, launch_update(A + j1 + j1 * lda, lda, (int)(m - j1), (int)(n - j1),
-                                  A + j1 + i * lda, lda, Wt + j1 * 64, 64, kb, s));
+                                  A + j1 + i * lda, lda, Wt + j1 * 64, 64, kb, h->update_wgs, s));
       }
       KTimer kt(h, K_QP3_ROW, 2.0 * (double)(m - j1) * (n - j1), 8.0 * (double)(m - j1) * (n - j1));
       hipLaunchKernelGGL(qp3_norms_kernel, dim3((unsigned)((n - j1 + 3) / 4)), dim3(256), 0, s, A,

@@ -225,6 +225,7 @@ rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t
     st = rq_create(&h, device, str);
     if (st != RQ_OK) break;
     h->max_groups = cap;
+    h->update_wgs = cap;
     s->handles.push_back(h);
     st = reserve(h, ws);
   }

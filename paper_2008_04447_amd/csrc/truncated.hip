@@ -283,7 +283,7 @@ static rq_status qr_blocked(rq_handle h, double* A, int64_t lda, int64_t M, int6
     }
     KTimer kt(h, K_UPDATE, 2.0 * bj * (double)Mj * Nt, 8.0 * 2.0 * Mj * (double)Nt);
     RQ_CHECK(h, launch_update(A + c0 + (c0 + bj) * lda, lda, (int)Mj, (int)Nt, w.ybuf, M, w.x1, 64,
-                              bj, s));
+                              bj, h->update_wgs, s));
   }
   return RQ_OK;
 }
@@ -320,7 +320,8 @@ static rq_status form_q(rq_handle h, const double* A, int64_t lda, int64_t M, in
                                   false, s));
     }
     KTimer kt(h, K_UPDATE, 2.0 * bj * (double)Mj * K, 8.0 * 2.0 * Mj * (double)K);
-    RQ_CHECK(h, launch_update(Q + c0, ldq, (int)Mj, (int)K, w.ybuf, M, w.x1, 64, bj, s));
+    RQ_CHECK(h, launch_update(Q + c0, ldq, (int)Mj, (int)K, w.ybuf, M, w.x1, 64, bj, h->update_wgs,
+                              s));
   }
   return RQ_OK;
 }
