@@ -102,7 +102,7 @@ rq_status sketch_fp64(rq_handle h, int ell, int64_t m, int64_t n, const double* 
 }
 
 static void plan_split32(int K, int N, int* ks, int* kc) {
-  plan_split(K, N, ks, kc);
+  plan_split_target(K, N, 64, 512, ks, kc);
   *kc = ((*kc + 31) / 32) * 32;
   *ks = (K + *kc - 1) / *kc;
   if (*ks < 1) *ks = 1;

@@ -193,13 +193,157 @@ __global__ __launch_bounds__(256, 2) void gemm_lx_kernel(GemmArgs g) {
   }
 }
 
-// Output columns per workgroup of gemm_lx for P rows.
-static int lx_cols(int P) { return P <= 64 ? 64 : 32; }
+// ---------------------------------------------------------------------------
+// gemm_lx for L with unit k stride and P <= 64 (the W = Y^T A of every block):
+// the same split of the work as gemm_lx_kernel with 32 output columns per
+// workgroup, one wave per SIMD and the operands of the next two 16-row groups
+// in flight while the matrix cores work on the current one (a ring of three
+// register sets, so no set is ever copied).  Rows of full groups are read
+// without masks; only a final partial group is masked.  Rows p >= P of L are
+// clamped to row P - 1: they only feed output rows that are not stored.
+template <int PB>
+__global__ __launch_bounds__(256, 1) void gemm_lx_ring_kernel(GemmArgs g) {
+  constexpr int NB = 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int kb = blockIdx.y * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  const int first = kb + 16 * wave;               // this wave's groups: first + 64 i
+  bool nok[NB];
+  const double* xp[NB];
+  const double* lp[PB];
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) {
+    const int n = blockIdx.x * 16 * NB + 16 * jb + l16;
+    nok[jb] = n < g.N;
+    xp[jb] = g.X + (nok[jb] ? (g.xcol ? g.xcol[n] : (int64_t)n) : 0) * g.ldx + first + 4 * kq;
+  }
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+    lp[i] = g.L + (int64_t)min(16 * i + l16, g.P - 1) * g.sLp + first + 4 * kq;
+  dx4 acc[PB][NB];
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) acc[i][jb] = dx4{0.0, 0.0, 0.0, 0.0};
+  struct Ops {
+    double la[PB][4], xb[NB][4];
+  };
+  auto load = [&](int grp, Ops& o) {
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) o.xb[jb][s] = xp[jb][64 * grp + s];
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) o.la[i][s] = lp[i][64 * grp + s];
+  };
+  auto compute = [&](const Ops& o) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < PB; ++i)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) acc[i][jb] = mfma_f64(o.la[i][s], o.xb[jb][s], acc[i][jb]);
+  };
+  const int nfull = (ke >= first + 16) ? (ke - first - 16) / 64 + 1 : 0;
+  {
+    Ops A, B, Cr;
+    if (nfull > 0) load(0, A);
+    if (nfull > 1) load(1, B);
+    for (int i = 0; i < nfull; i += 3) {
+      if (i + 2 < nfull) load(i + 2, Cr);
+      compute(A);
+      if (i + 1 >= nfull) break;
+      if (i + 3 < nfull) load(i + 3, A);
+      compute(B);
+      if (i + 2 >= nfull) break;
+      if (i + 4 < nfull) load(i + 4, B);
+      compute(Cr);
+    }
+  }
+  {
+    const int k0 = first + 64 * nfull;            // a final partial group
+    if (k0 < ke) {
+      Ops o;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool kok = k0 + 4 * kq + s < ke;
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) o.xb[jb][s] = kok ? xp[jb][64 * nfull + s] : 0.0;
+#pragma unroll
+        for (int i = 0; i < PB; ++i) o.la[i][s] = kok ? lp[i][64 * nfull + s] : 0.0;
+      }
+      compute(o);
+    }
+  }
+  // ---- combine the four waves: (w0 + w2) + (w1 + w3) ---------------------------
+  constexpr int E = PB * NB * 4;
+  __shared__ double s_red[2][E][64];
+  if (wave >= 2) {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_red[wave - 2][(i * NB + jb) * 4 + v][lane] = acc[i][jb][v];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][jb][v] += s_red[wave][(i * NB + jb) * 4 + v][lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_red[0][(i * NB + jb) * 4 + v][lane] = acc[i][jb][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][jb][v] += s_red[0][(i * NB + jb) * 4 + v][lane];
+  // lane holds D[16 i + kq + 4 v][column 16 jb + l16]
+  double* o = g.out + (g.ksplit > 1 ? (int64_t)blockIdx.y * g.split_stride : 0);
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) {
+    if (!nok[jb]) continue;
+    const int64_t n = blockIdx.x * 16 * NB + 16 * jb + l16;
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * i + kq + 4 * v;
+        if (p >= g.P) continue;
+        if (g.ksplit > 1) {
+          o[p + n * g.ldout] = acc[i][jb][v];
+        } else {
+          double r = g.alpha * acc[i][jb][v];
+          if (g.beta != 0.0) r += g.beta * g.C[p + n * g.ldc];
+          o[p + n * g.ldout] = r;
+        }
+      }
+  }
+}
 
-void plan_split(int K, int N, int* ksplit, int* kchunk, int P) {
-  const int tiles = (N + lx_cols(P) - 1) / lx_cols(P);
-  int ks = (512 + tiles - 1) / tiles;              // about two workgroups per CU
-  const int kmax = (K + 255) / 256;                // at least 64 rows per wave
+// Split of K for a product with N output columns: about `target` workgroups
+// of `cols` columns each, at least 64 rows per wave, chunks a multiple of 64.
+void plan_split_target(int K, int N, int cols, int target, int* ksplit, int* kchunk) {
+  const int tiles = (N + cols - 1) / cols;
+  int ks = (target + tiles - 1) / tiles;
+  const int kmax = (K + 255) / 256;
   if (ks > kmax) ks = kmax;
   if (ks > 32) ks = 32;
   if (ks < 1) ks = 1;
@@ -210,6 +354,12 @@ void plan_split(int K, int N, int* ksplit, int* kchunk, int P) {
   if (ks < 1) ks = 1;
   *ksplit = ks;
   *kchunk = kc;
+}
+
+// FP64 gemm_lx: 32 output columns per workgroup; one workgroup per CU for the
+// ring kernel (P <= 64), two for the general kernel.
+void plan_split(int K, int N, int* ksplit, int* kchunk, int P) {
+  plan_split_target(K, N, 32, P <= 64 ? 256 : 512, ksplit, kchunk);
 }
 
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
@@ -229,8 +379,18 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
     }
     return hipGetLastError();
   }
-  dim3 grid((g.N + lx_cols(g.P) - 1) / lx_cols(g.P), g.ksplit);
   const bool lk1 = g.sLk == 1;
+  if (lk1 && pb <= 4) {
+    dim3 grid((g.N + 31) / 32, g.ksplit);
+    switch (pb) {
+      case 1: hipLaunchKernelGGL(gemm_lx_ring_kernel<1>, grid, dim3(256), 0, s, g); break;
+      case 2: hipLaunchKernelGGL(gemm_lx_ring_kernel<2>, grid, dim3(256), 0, s, g); break;
+      case 3: hipLaunchKernelGGL(gemm_lx_ring_kernel<3>, grid, dim3(256), 0, s, g); break;
+      default: hipLaunchKernelGGL(gemm_lx_ring_kernel<4>, grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError();
+  }
+  dim3 grid((g.N + (g.P <= 64 ? 63 : 31)) / (g.P <= 64 ? 64 : 32), g.ksplit);
 #define RQ_LX(pb_, nb_)                                                                  \
   case pb_:                                                                              \
     if (lk1)                                                                             \

@@ -63,6 +63,7 @@ struct GemmArgs {
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
 // split-K plan of launch_gemm_lx for P output rows (kchunk a multiple of 64)
 void plan_split(int K, int N, int* ksplit, int* kchunk, int P = 64);
+void plan_split_target(int K, int N, int cols, int target, int* ksplit, int* kchunk);
 
 // ---- BF16 MFMA contractions (FP32 accumulate, FP64 results) -----------------
 struct GemmArgsF {
