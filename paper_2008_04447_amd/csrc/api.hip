@@ -164,8 +164,12 @@ size_t sq_rec_doubles(int ell, int64_t N) {
   return (size_t)RQ_MAX_B * sq_max_groups(N) * sq_record_stride(lm);   // one slot per step
 }
 
+static int panel_groups(int64_t M);
+static int64_t panel_prep_words(int64_t M, int bj);
+
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
-                          SqWork w, int64_t* perm, hipEvent_t queued) {
+                          SqWork w, int64_t* perm, hipEvent_t queued, double* panel_rec,
+                          int64_t panel_m, int panel_bj) {
   const int lm = sq_lm(ell);
   SqArgs a{};
   a.B = B;
@@ -182,7 +186,11 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.src_top = w.src_top;
   a.dst_low = w.dst_low;
   a.perm = perm;
-  RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
+  if (panel_rec)
+    RQ_CHECK(h, launch_exchange_prep2(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, panel_rec,
+                                      panel_prep_words(panel_m, panel_bj), h->stream));
+  else
+    RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
   KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
   if (queued) RQ_CHECK(h, hipEventRecord(queued, h->stream));
   RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
@@ -191,12 +199,20 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
 
 static int panel_groups(int64_t M) { return (int)((M + kPanelRows - 1) / kPanelRows); }
 
+// Record words a panel of M rows and bj columns uses: the column-by-column
+// route's, then (bj >= 2) the Cholesky-QR route's.
+static int64_t panel_prep_words(int64_t M, int bj) {
+  const int nwg = panel_groups(M);
+  const int64_t hh = (int64_t)(bj + 1) * nwg * 3 * 64;
+  return hh + (bj >= 2 ? panel_cholqr_doubles(nwg) : 0);
+}
+
 size_t panel_rec_doubles(int64_t M) {
   return (size_t)(RQ_MAX_B + 1) * panel_groups(M) * 3 * 64 + (size_t)panel_cholqr_doubles(panel_groups(M));
 }
 
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
-                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt) {
+                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt, bool prepared) {
   PanelArgs a{};
   a.A = A;
   a.lda = lda;
@@ -216,8 +232,7 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
   const int64_t hh = (int64_t)(bj + 1) * a.nwg * 3 * 64;
   a.crec = bj >= 2 ? rec + hh : nullptr;
   a.fallback = a.crec ? h->sync + 2 : nullptr;
-  RQ_CHECK(h, launch_exchange_prep(h->sync, rec, hh + (a.crec ? panel_cholqr_doubles(a.nwg) : 0),
-                                   h->stream));
+  if (!prepared) RQ_CHECK(h, launch_exchange_prep(h->sync, rec, panel_prep_words(M, bj), h->stream));
   KTimer kt(h, K_PANEL, 2.0 * (double)M * bj * bj, 8.0 * (double)M * (2.0 * bj + 64));
   RQ_CHECK(h, launch_panel(a, h->stream));
   return RQ_OK;
@@ -232,9 +247,9 @@ rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R1
     RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, h->stream));
   }
   GemmArgs u{};
-  u.L = mhat;
-  u.sLp = 1;
-  u.sLk = 64;
+  u.L = mhat;                       // Mhat transposed: L(p, k) = mhat[k + 64 p]
+  u.sLp = 64;
+  u.sLk = 1;
   u.X = R12;
   u.ldx = ldr12;
   u.P = bj;
@@ -528,7 +543,7 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     double* Ablk = A + col0 + col0 * lda;            // trailing block A(col0:, col0:)
     // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
     RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr,
-                           side_queued ? h->ev_z : nullptr));
+                           side_queued ? h->ev_z : nullptr, prec, M, bj));
     if (side_queued) RQ_TRY(release_side(sq_groups(N, h->max_groups)));
     // the previous block's update of rows below its R12 must be complete
     if (pending_rows) {
@@ -541,12 +556,11 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_CHECK(h, launch_permute(A + col0 * lda, lda, (int)m, bj, sw.src_top, sw.dst_low,
                                  jpvt + col0, s));
     }
-    // 3. panel QR of the b selected columns and T of the block
-    RQ_TRY(run_panel(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tblk, 64));
-    if (T) {
-      KTimer kt(h, K_OTHER, 0.0, 16.0 * bj * bj);
-      RQ_CHECK(h, launch_copy2d(tblk, 64, T + col0 * ldt, ldt, bj, bj, s));
-    }
+    // 3. panel QR of the b selected columns and T of the block (written straight
+    // into the caller's T when there is one: only its bj x bj block is touched)
+    double* tj = T ? T + col0 * ldt : tblk;
+    const int64_t ldtj = T ? ldt : 64;
+    RQ_TRY(run_panel(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tj, ldtj, true));
     const int64_t Nt = N - bj;
     if (Nt <= 0) continue;
     double* Ctr = Ablk + bj * lda;                   // A(col0:, col0+bj:)
@@ -575,21 +589,17 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_CHECK(h, launch_gemm_lx(g, s));
     }
     {
-      KTimer kt(h, K_REDUCE, (double)bj * bj * Nt + (double)(ks - 1) * bj * Nt,
-                8.0 * ((double)ks * bj * Nt + 64.0 * Nt));
-      RQ_CHECK(h, launch_reduce(part, 64, g.split_stride, ks, bj, (int)Nt, zbuf, 64, tblk, 64,
-                                bj, s));
+      // with step 5 for rows 0..bj-1 (R12 -= Y11 Z): the sample update and the
+      // next block's sample QRCP need only them
+      KTimer kt(h, K_REDUCE,
+                (double)bj * bj * Nt + (double)(ks - 1) * bj * Nt + 2.0 * bj * (double)bj * Nt,
+                8.0 * ((double)ks * bj * Nt + 64.0 * Nt + 2.0 * bj * (double)Nt));
+      RQ_CHECK(h, launch_reduce_r12(part, g.split_stride, ks, (int)Nt, zbuf, tj, ldtj, ybuf, m,
+                                    Ctr, lda, bj, s));
     }
-    // 5. A_trailing -= Y Z.  Rows 0..bj-1 (R12) are updated on the main stream:
-    // the sample update and the next block's sample QRCP need only them.  The
-    // other rows go to the side stream alongside the next sample QRCP (see
-    // release_side); the next block waits for them before it permutes and
-    // factors its panel.
-    {
-      KTimer kt(h, K_UPDATE, 2.0 * bj * (double)bj * Nt,
-                8.0 * (2.0 * bj * Nt + (double)bj * bj + (double)bj * Nt));
-      RQ_CHECK(h, launch_update(Ctr, lda, bj, (int)Nt, ybuf, m, zbuf, 64, bj, h->update_wgs, s));
-    }
+    // 5. A_trailing -= Y Z for the rows below R12: on the side stream alongside
+    // the next sample QRCP (see release_side); the next block waits for them
+    // before it permutes and factors its panel.
     // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
     if (col0 + bj < k)
       RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,

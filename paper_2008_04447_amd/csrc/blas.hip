@@ -366,6 +366,17 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
   if (g.N <= 0 || g.P <= 0) return hipSuccess;
   if (g.kchunk <= 0 || g.kchunk % 16 != 0) return hipErrorInvalidValue;
   const int pb = (g.P + 15) / 16;
+  const bool lk1 = g.sLk == 1;
+  if (lk1 && pb <= 4 && g.kchunk > 64) {
+    dim3 grid((g.N + 31) / 32, g.ksplit);
+    switch (pb) {
+      case 1: hipLaunchKernelGGL(gemm_lx_ring_kernel<1>, grid, dim3(256), 0, s, g); break;
+      case 2: hipLaunchKernelGGL(gemm_lx_ring_kernel<2>, grid, dim3(256), 0, s, g); break;
+      case 3: hipLaunchKernelGGL(gemm_lx_ring_kernel<3>, grid, dim3(256), 0, s, g); break;
+      default: hipLaunchKernelGGL(gemm_lx_ring_kernel<4>, grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError();
+  }
   if (g.kchunk <= 64) {
     dim3 grid((g.N + 63) / 64, g.ksplit);
     switch (pb) {
@@ -376,17 +387,6 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
       case 5: hipLaunchKernelGGL(gemm_lx_narrow_kernel<5>, grid, dim3(256), 0, s, g); break;
       case 6: hipLaunchKernelGGL(gemm_lx_narrow_kernel<6>, grid, dim3(256), 0, s, g); break;
       default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-  const bool lk1 = g.sLk == 1;
-  if (lk1 && pb <= 4) {
-    dim3 grid((g.N + 31) / 32, g.ksplit);
-    switch (pb) {
-      case 1: hipLaunchKernelGGL(gemm_lx_ring_kernel<1>, grid, dim3(256), 0, s, g); break;
-      case 2: hipLaunchKernelGGL(gemm_lx_ring_kernel<2>, grid, dim3(256), 0, s, g); break;
-      case 3: hipLaunchKernelGGL(gemm_lx_ring_kernel<3>, grid, dim3(256), 0, s, g); break;
-      default: hipLaunchKernelGGL(gemm_lx_ring_kernel<4>, grid, dim3(256), 0, s, g); break;
     }
     return hipGetLastError();
   }
@@ -457,6 +457,70 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64
     Z[i + n * ldz] = z;
   else if (zero_pad && i < ldz)
     Z[i + n * ldz] = 0.0;
+}
+
+// reduce + R12 update of one block (steps 4 and 5 of Algorithm 4 for the rows
+// of R12): W(:, n) = sum_s part_s(:, n) in order s = 0, 1, ...; Z(:, n) =
+// T^T W(:, n) (rows bj..63 of Z zero); R12(:, n) -= Y11 Z(:, n), with Y11 the
+// leading bj x bj block of Y.  A workgroup takes 16 columns (4 per wave), so
+// that T and Y11 are staged in LDS once for all of them.
+__global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, int64_t sstride,
+                                                           int ks, int N, double* Z,
+                                                           const double* T, int64_t ldt,
+                                                           const double* Y, int64_t ldy,
+                                                           double* R12, int64_t ldr, int bj) {
+  __shared__ double s_T[64][65];   // s_T[q][i] = T(q, i), upper triangle
+  __shared__ double s_Y[64][65];   // s_Y[r][i] = Y(r, i), r, i < bj
+  __shared__ double s_v[4][64];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int a = e % 64, b = e / 64;
+    s_T[a][b] = (a < bj && b < bj && a <= b) ? T[a + (int64_t)b * ldt] : 0.0;
+    s_Y[a][b] = (a < bj && b < bj) ? Y[a + (int64_t)b * ldy] : 0.0;
+  }
+  const int i = threadIdx.x & 63;
+  const int cl = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll 1
+  for (int it = 0; it < 4; ++it) {
+    const int64_t n = (int64_t)blockIdx.x * 16 + 4 * it + cl;   // uniform per wave
+    if (n >= N) break;
+    double w = 0.0;
+    if (i < bj)
+      for (int r = 0; r < ks; ++r) w += part[r * sstride + i + n * 64];
+    s_v[cl][i] = w;
+    // the wave's own LDS writes are visible to its later reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double z = 0.0;
+#pragma unroll 16
+    for (int q = 0; q < 64; ++q) z += s_T[q][i] * s_v[cl][q];
+    Z[i + n * 64] = (i < bj) ? z : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    s_v[cl][i] = (i < bj) ? z : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double u = 0.0;
+#pragma unroll 16
+    for (int q = 0; q < 64; ++q) u += s_Y[i][q] * s_v[cl][q];
+    if (i < bj) R12[i + n * ldr] -= u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+hipError_t launch_reduce_r12(const double* part, int64_t sstride, int ks, int N, double* Z,
+                             const double* T, int64_t ldt, const double* Y, int64_t ldy,
+                             double* R12, int64_t ldr, int bj, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  if (bj < 1 || bj > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reduce_t_r12_kernel, dim3((N + 15) / 16), dim3(256), 0, s, part, sstride, ks,
+                     N, Z, T, ldt, Y, ldy, R12, ldr, bj);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P, int N,
@@ -676,36 +740,39 @@ hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, 
 }
 
 // ---------------------------------------------------------------------------
-// omega11: one wave per row i of M = S11 R11^{-1}; lane c holds row i's
-// right-hand side entry c and column c of R11.  Column-oriented substitution:
-// m_c = s_c / R_cc, then s_c' -= m_c R_cc' for c' > c.
-__global__ __launch_bounds__(256) void omega11_kernel(const double* S11, int64_t lds,
-                                                      const double* R11, int64_t ldr, int bj,
-                                                      double* M, int64_t ldm) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= bj) return;
+// omega11: Mhat = S11 R11^{-1} (both bj x bj upper triangular, so Mhat is too),
+// written transposed: Mt(k, i) = Mhat(i, k).  One single-wave workgroup per row
+// i (rows on different compute units); lane c holds column c of R11 in
+// registers and the reciprocal of R11(c, c).  Step c: m_c = s_c / R(c, c), then
+// s_c' -= m_c R(c, c') for c' > c, with s_c and 1 / R(c, c) read from lane c by
+// v_readlane.
+__global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t lds,
+                                                     const double* R11, int64_t ldr, int bj,
+                                                     double* Mt, int64_t ldm) {
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x;
   double rc[64];
 #pragma unroll
-  for (int q = 0; q < 64; ++q) rc[q] = (lane < bj && q <= lane) ? R11[q + (int64_t)lane * ldr] : 0.0;
+  for (int q = 0; q < 64; ++q)
+    rc[q] = (lane < bj && q <= lane) ? R11[q + (int64_t)lane * ldr] : 0.0;
+  const double rinv = (lane < bj) ? 1.0 / R11[lane + (int64_t)lane * ldr] : 0.0;
   double sv = (lane < bj && lane >= i) ? S11[i + (int64_t)lane * lds] : 0.0;
   double mine = 0.0;
 #pragma unroll
   for (int c = 0; c < 64; ++c) {
     if (c < bj) {
-      const double d = __shfl(rc[c], c, 64);      // R11(c, c)
-      const double mc = __shfl(sv, c, 64) / d;
+      const double mc = readlane_f64(sv, c) * readlane_f64(rinv, c);
       if (lane == c) mine = mc;
-      if (lane > c) sv -= mc * rc[c];             // rc[c] = R11(c, lane)
+      if (lane > c) sv = fma(-mc, rc[c], sv);   // rc[c] = R11(c, lane)
     }
   }
-  if (lane < bj) M[i + (int64_t)lane * ldm] = mine;
+  if (lane < bj) Mt[lane + (int64_t)i * ldm] = mine;
 }
 
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr, int bj,
-                          double* M, int64_t ldm, hipStream_t s) {
-  hipLaunchKernelGGL(omega11_kernel, dim3((bj + 3) / 4), dim3(256), 0, s, S11, lds, R11, ldr,
-                     bj, M, ldm);
+                          double* Mt, int64_t ldm, hipStream_t s) {
+  if (bj < 1 || bj > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(omega11_kernel, dim3(bj), dim3(64), 0, s, S11, lds, R11, ldr, bj, Mt, ldm);
   return hipGetLastError();
 }
 
@@ -784,6 +851,26 @@ hipError_t launch_exchange_prep(uint32_t* sync, double* rec, int64_t n, hipStrea
   const int64_t total = n > 3 ? n : 3;
   hipLaunchKernelGGL(exchange_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      sync, reinterpret_cast<unsigned long long*>(rec), n);
+  return hipGetLastError();
+}
+
+// The same for two record areas in one launch (words [0, n1) of rec1, then
+// [0, n2) of rec2).
+__global__ void exchange_prep2_kernel(uint32_t* sync, unsigned long long* rec1, int64_t n1,
+                                      unsigned long long* rec2, int64_t n2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < 3) sync[e] = 0u;
+  if (e < n1)
+    rec1[e] = kUnpublished;
+  else if (e - n1 < n2)
+    rec2[e - n1] = kUnpublished;
+}
+hipError_t launch_exchange_prep2(uint32_t* sync, double* rec1, int64_t n1, double* rec2,
+                                 int64_t n2, hipStream_t s) {
+  const int64_t total = std::max<int64_t>(n1 + n2, 3);
+  hipLaunchKernelGGL(exchange_prep2_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     s, sync, reinterpret_cast<unsigned long long*>(rec1), n1,
+                     reinterpret_cast<unsigned long long*>(rec2), n2);
   return hipGetLastError();
 }
 

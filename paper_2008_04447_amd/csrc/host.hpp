@@ -156,10 +156,15 @@ inline size_t bf16_stage_doubles(int64_t K) { return (size_t)(bf16_stage_elems(K
 size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
 // `queued`, when given, is recorded on the handle's stream right before the
 // kernel launch (work that waits on it becomes ready together with the launch).
+// `panel_rec`, when given, is the record area of the panel that follows (M
+// rows, bj columns): it is prepared together with the sample's records, and
+// that panel is then run with `prepared` set.
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
-                          SqWork w, int64_t* perm, hipEvent_t queued = nullptr);
+                          SqWork w, int64_t* perm, hipEvent_t queued = nullptr,
+                          double* panel_rec = nullptr, int64_t panel_m = 0, int panel_bj = 0);
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
-                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt);
+                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt,
+                    bool prepared = false);
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
                             const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat);
 // Workspace bytes trqrcp_truncate / tuxv_svd reserve for a problem shape.

@@ -86,6 +86,11 @@ hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float
 
 // sum of split-K partials; with T != null the result is Z = T^T W written with
 // leading dimension ldz = 64 (rows bj..63 zero) -- the trailing-update operand.
+// Fixed-order sum of ks split-K partials (ld 64) into W, Z = T^T W (64 x N, rows
+// bj.. zero) and R12(bj x N) -= Y11 Z, Y11 the leading bj x bj block of Y.
+hipError_t launch_reduce_r12(const double* part, int64_t sstride, int ks, int N, double* Z,
+                             const double* T, int64_t ldt, const double* Y, int64_t ldy,
+                             double* R12, int64_t ldr, int bj, hipStream_t s);
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P,
                          int N, double* out, int64_t ldout, const double* T, int64_t ldt,
                          int bj, hipStream_t s);
@@ -125,9 +130,10 @@ hipError_t launch_tcompose(double* T, int64_t ldt, int c0, int bj, const double*
 hipError_t launch_scatter_t(const double* R, int64_t ldr, int k, int n, const int64_t* col,
                             double* Z0T, int64_t ldz, hipStream_t s);
 
-// Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr.
+// Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr,
+// stored transposed: Mt[k + i ldm] = Omega_hat_11(i, k).
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr,
-                          int bj, double* M, int64_t ldm, hipStream_t s);
+                          int bj, double* Mt, int64_t ldm, hipStream_t s);
 
 // Column permutation of `rows` x (cols col0..) of X given by src_top/dst_low,
 // plus the same permutation of jpvt (int64, may be null).
@@ -139,6 +145,8 @@ hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s);
 // Clears the barrier counter, abort flag and panel fallback flag (sync[0..2]) and marks the n record
 // words of a persistent kernel's exchange as unpublished.
 hipError_t launch_exchange_prep(uint32_t* sync, double* rec, int64_t n, hipStream_t s);
+hipError_t launch_exchange_prep2(uint32_t* sync, double* rec1, int64_t n1, double* rec2,
+                                 int64_t n2, hipStream_t s);
 hipError_t launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,
                          int cols, hipStream_t s);
 
