@@ -247,9 +247,9 @@ rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R1
     RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, h->stream));
   }
   GemmArgs u{};
-  u.L = mhat;                       // Mhat transposed: L(p, k) = mhat[k + 64 p]
-  u.sLp = 64;
-  u.sLk = 1;
+  u.L = mhat;
+  u.sLp = 1;
+  u.sLk = 64;
   u.X = R12;
   u.ldx = ldr12;
   u.P = bj;

@@ -741,14 +741,14 @@ hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, 
 
 // ---------------------------------------------------------------------------
 // omega11: Mhat = S11 R11^{-1} (both bj x bj upper triangular, so Mhat is too),
-// written transposed: Mt(k, i) = Mhat(i, k).  One single-wave workgroup per row
+// M[i + c ldm] = Mhat(i, c).  One single-wave workgroup per row
 // i (rows on different compute units); lane c holds column c of R11 in
 // registers and the reciprocal of R11(c, c).  Step c: m_c = s_c / R(c, c), then
 // s_c' -= m_c R(c, c') for c' > c, with s_c and 1 / R(c, c) read from lane c by
 // v_readlane.
 __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t lds,
                                                      const double* R11, int64_t ldr, int bj,
-                                                     double* Mt, int64_t ldm) {
+                                                     double* M, int64_t ldm) {
   const int lane = threadIdx.x;
   const int i = blockIdx.x;
   double rc[64];
@@ -766,13 +766,13 @@ __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t 
       if (lane > c) sv = fma(-mc, rc[c], sv);   // rc[c] = R11(c, lane)
     }
   }
-  if (lane < bj) Mt[lane + (int64_t)i * ldm] = mine;
+  if (lane < bj) M[i + (int64_t)lane * ldm] = mine;
 }
 
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr, int bj,
-                          double* Mt, int64_t ldm, hipStream_t s) {
+                          double* M, int64_t ldm, hipStream_t s) {
   if (bj < 1 || bj > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(omega11_kernel, dim3(bj), dim3(64), 0, s, S11, lds, R11, ldr, bj, Mt, ldm);
+  hipLaunchKernelGGL(omega11_kernel, dim3(bj), dim3(64), 0, s, S11, lds, R11, ldr, bj, M, ldm);
   return hipGetLastError();
 }
 

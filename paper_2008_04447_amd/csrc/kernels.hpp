@@ -130,10 +130,9 @@ hipError_t launch_tcompose(double* T, int64_t ldt, int c0, int bj, const double*
 hipError_t launch_scatter_t(const double* R, int64_t ldr, int k, int n, const int64_t* col,
                             double* Z0T, int64_t ldz, hipStream_t s);
 
-// Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr,
-// stored transposed: Mt[k + i ldm] = Omega_hat_11(i, k).
+// Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr.
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr,
-                          int bj, double* Mt, int64_t ldm, hipStream_t s);
+                          int bj, double* M, int64_t ldm, hipStream_t s);
 
 // Column permutation of `rows` x (cols col0..) of X given by src_top/dst_low,
 // plus the same permutation of jpvt (int64, may be null).

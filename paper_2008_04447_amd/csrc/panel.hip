@@ -332,7 +332,42 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
       // pass 2
       tile_gram(x, X, e3 + (int64_t)wg * kWords, t);
       if (!gram_allreduce(e3, e4, G, X, a.nwg, wg, t, a.abort_flag, a.status)) return;
-      if (!chol_inv(G, D, diag, bj, t) && t == 0) raise_status(a.status, kErrNonFinite);
+      // G = Q1^T Q1 = I + E, E of the order of kappa^2 eps.  With max |E| <= 1e-10
+      // the factor and its inverse have closed forms to within rounding:
+      // R2 = I + F, F = triu(E) - diag(E) / 2, since R2^T R2 - G = F^T F, and
+      // R2^{-1} = I - F, since (I + F)(I - F) = I - F^2, both with entries of at
+      // most 64 max|E|^2 <= 1e-18.  Otherwise (and for non-finite G) the
+      // Cholesky sweep; every workgroup holds the same G and decides alike.
+      double em = 0.0;
+      for (int e = t; e < kPC * kPC; e += kPanelThreads) {
+        const int i = e >> 6, j = e & 63;
+        if (i < bj && j < bj && i <= j) {
+          const double v = fabs(G[i * kLd + j] - (i == j ? 1.0 : 0.0));
+          em = (v > em || v != v) ? v : em;
+        }
+      }
+      if (!__syncthreads_or(!(em <= 1e-10))) {
+        // R2 transposed into G's lower part and its diagonal into diag, as the
+        // sweep leaves them; D = R2^{-1} (upper)
+        for (int e = t; e < kPC * kLd; e += kPanelThreads) {
+          const int i = e / kLd, j = e - i * kLd;
+          double dv = 0.0;
+          if (i < bj && j < bj) {
+            if (i == j) {
+              diag[i] = 0.5 * (1.0 + G[i * kLd + i]);
+              dv = 0.5 * (3.0 - G[i * kLd + i]);
+            } else if (i < j) {
+              const double f = G[i * kLd + j];
+              G[j * kLd + i] = f;
+              dv = -f;
+            }
+          }
+          D[e] = dv;
+        }
+        __syncthreads();
+      } else if (!chol_inv(G, D, diag, bj, t) && t == 0) {
+        raise_status(a.status, kErrNonFinite);
+      }
       tile_times(x, X, D, t, rbase, 0);                          // Q = Q1 R2^{-1}
       if (wg == 0) {
         // R = R2 R1 into D (R2 upper: diag and G's lower part transposed)
