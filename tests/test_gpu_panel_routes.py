@@ -95,3 +95,36 @@ def test_cholqr_route_shapes(api, m, n, b):
         _check_tall(a, om, b, p, k, qr, jpvt, tau, T)
     else:
         _check_against_oracle(a, om, b, p, k, qr, jpvt, tau, T, min_prefix=1)
+
+
+def _second_pass_offset(a, jpvt, b):
+    """max |Q1^T Q1 - I| after one Cholesky-QR pass over the first panel (the
+    quantity that selects the closed form of the second pass), in numpy FP64."""
+    x = a[:, jpvt[:b]]
+    r1 = np.linalg.cholesky(x.T @ x).T
+    q1 = np.linalg.solve(r1.T, x.T).T
+    return float(np.abs(q1.T @ q1 - np.eye(b)).max())
+
+
+@pytest.mark.parametrize("kappa", [1.0, 3e4])
+def test_second_pass_routes(api, kappa):
+    """The second Cholesky-QR pass of a tall panel: with a well-conditioned
+    panel its Gram matrix is the identity to ~1e-15 and the closed form
+    R2 = I + F is used; at condition number 3e4 the offset is ~6e-9, well above
+    the 1e-10 gate, and the Cholesky sweep runs (the first factor's diagonal
+    ratio, ~4.4e3, keeps the Cholesky-QR route).  Both against the oracle."""
+    m, b, p = 3000, 64, 8
+    n = k = b
+    sig = np.geomspace(1.0, 1.0 / kappa, n)
+    a = np.asfortranarray(synth.low_rank(m, n, sig, 5200, 5201))
+    om = synth.omega(b + p, m, 5202)
+    ref = oracle.rqrcp(a, om, b, p, k=k)
+    off = _second_pass_offset(a, ref.jpvt, b)
+    if kappa == 1.0:
+        assert off <= 1e-13, off
+    else:
+        assert off >= 1e-9, off
+    ratios = _panel_diag_ratios(a, om, b, p, k)
+    assert ratios[0] <= GATE / 2, ratios            # the Cholesky-QR route in both cases
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, k, a, om)
+    _check_tall(a, om, b, p, k, qr, jpvt, tau, T)
