@@ -91,6 +91,7 @@ RQ_DEV bool wait_words(Src src, int total, Put put, int t, uint32_t* abort_flag,
 // false when a pivot is not positive or not finite (same value in all threads).
 RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
   const int g = t & 15, row = t >> 4;
+  const int lane = t & 63, wave = t >> 6;     // wave w owns rows 4w..4w+3 of both parts
   for (int e = t; e < kPC * kLd; e += kPanelThreads) Minv[e] = 0.0;
   __syncthreads();
   bool ok = true;
@@ -100,25 +101,30 @@ RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
     const double rinv = rsqrt_nr(d);
     const double rkk = d * rinv;
     const double dinv = rinv * rinv;
-    // trailing update of the upper part: A[i][j] -= A[k][i] A[k][j] / d, k < i <= j < n
+    // trailing update of the upper part: A[i][j] -= A[k][i] A[k][j] / d, k < i <= j < n,
+    // lane = column j; waves whose rows are all <= k issue nothing
+    if (4 * wave + 3 > k) {
+      const double ckj = A[k * kLd + lane] * dinv;
 #pragma unroll
-    for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
-      const int e = t + q * kPanelThreads;
-      const int i = e >> 6, j = e & 63;
-      if (i > k && j >= i && j < n) A[i * kLd + j] -= A[k * kLd + i] * A[k * kLd + j] * dinv;
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * wave + q;
+        if (i > k && lane >= i && lane < n) A[i * kLd + lane] -= A[k * kLd + i] * ckj;
+      }
     }
     // row k of R, stored transposed below the diagonal
     if (t > k && t < n) A[t * kLd + k] = A[k * kLd + t] * rinv;
     if (t == 0) diag[k] = rkk;
-    // column k of R^{-1}: 16 lanes per row
-    double acc = 0.0;
-    for (int l = row + g; l < k; l += 16) acc += Minv[row * kLd + l] * A[k * kLd + l];
-    acc = row16_sum(acc);
-    if (g == 0) {
-      if (row < k)
-        Minv[row * kLd + k] = -acc * rinv;
-      else if (row == k)
-        Minv[k * kLd + k] = rinv;
+    // column k of R^{-1}: 16 lanes per row (rows beyond k issue nothing)
+    if (4 * wave <= k) {
+      double acc = 0.0;
+      for (int l = row + g; l < k; l += 16) acc += Minv[row * kLd + l] * A[k * kLd + l];
+      acc = row16_sum(acc);
+      if (g == 0) {
+        if (row < k)
+          Minv[row * kLd + k] = -acc * rinv;
+        else if (row == k)
+          Minv[k * kLd + k] = rinv;
+      }
     }
     __syncthreads();
   }
@@ -134,6 +140,7 @@ RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
 RQ_DEV void lu_signed(double* A, double* Z, double* W, double* sgn, double* udiag, double* rcp,
                       int n, int t) {
   const int g = t & 15, row = t >> 4;
+  const int lane = t & 63, wave = t >> 6;     // wave w owns rows 4w..4w+3 of both parts
   for (int e = t; e < kPC * kLd; e += kPanelThreads) {
     Z[e] = 0.0;
     W[e] = 0.0;
@@ -144,32 +151,39 @@ RQ_DEV void lu_signed(double* A, double* Z, double* W, double* sgn, double* udia
     const double sk = (p >= 0.0) ? -1.0 : 1.0;
     const double ukk = p - sk;
     const double uinv = rcp_nr(ukk);
+    // trailing update A[i][j] -= L[i][k] U[k][j], lane = column j; waves whose
+    // rows are all <= k issue nothing
+    if (4 * wave + 3 > k) {
+      const double ukj = uinv * A[k * kLd + lane];
 #pragma unroll
-    for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
-      const int e = t + q * kPanelThreads;
-      const int i = e >> 6, j = e & 63;
-      if (i > k && j > k && i < n && j < n) A[i * kLd + j] -= A[i * kLd + k] * uinv * A[k * kLd + j];
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * wave + q;
+        if (i > k && i < n && lane > k && lane < n) A[i * kLd + lane] -= A[i * kLd + k] * ukj;
+      }
     }
     if (t == 0) {
       sgn[k] = sk;
       udiag[k] = ukk;
       rcp[k] = uinv;
     }
-    // column k of U^{-1} (rows row < k) and row k of L^{-1} (columns row < k)
-    double az = 0.0, aw = 0.0;
-    for (int l = row + g; l < k; l += 16) {
-      az += Z[row * kLd + l] * A[l * kLd + k];
-      aw += A[k * kLd + l] * rcp[l] * W[l * kLd + row];
-    }
-    az = row16_sum(az);
-    aw = row16_sum(aw);
-    if (g == 0) {
-      if (row < k) {
-        Z[row * kLd + k] = -az * uinv;
-        W[k * kLd + row] = -aw;
-      } else if (row == k) {
-        Z[k * kLd + k] = uinv;
-        W[k * kLd + k] = 1.0;
+    // column k of U^{-1} (rows row < k) and row k of L^{-1} (columns row < k);
+    // rows beyond k issue nothing
+    if (4 * wave <= k) {
+      double az = 0.0, aw = 0.0;
+      for (int l = row + g; l < k; l += 16) {
+        az += Z[row * kLd + l] * A[l * kLd + k];
+        aw += A[k * kLd + l] * rcp[l] * W[l * kLd + row];
+      }
+      az = row16_sum(az);
+      aw = row16_sum(aw);
+      if (g == 0) {
+        if (row < k) {
+          Z[row * kLd + k] = -az * uinv;
+          W[k * kLd + row] = -aw;
+        } else if (row == k) {
+          Z[k * kLd + k] = uinv;
+          W[k * kLd + k] = 1.0;
+        }
       }
     }
     __syncthreads();
