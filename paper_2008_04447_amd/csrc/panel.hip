@@ -384,13 +384,24 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
       }
       tile_times(x, X, D, t, rbase, 0);                          // Q = Q1 R2^{-1}
       if (wg == 0) {
+        // the 16 x 16 block (bp, bq) of a 64 x 64 product per wave, on the
+        // matrix cores; lane holds rows 16 bp + kq + 4 v, column 16 bq + l16
+        const int lane = t & 63, wave = t >> 6;
+        const int bp = wave >> 2, bq = wave & 3, l16 = lane & 15, kq = lane >> 4;
+        const int brow = 16 * bp + l16;                           // A-operand row of this lane
         // R = R2 R1 into D (R2 upper: diag and G's lower part transposed)
-        for (int e = t; e < kPC * kPC; e += kPanelThreads) {
-          const int i = e >> 6, j = e & 63;
-          double s = 0.0;
-          if (i < bj && j < bj && i <= j)
-            for (int k = i; k <= j; ++k) s += (k == i ? diag[i] : G[k * kLd + i]) * RB[k * kLd + j];
-          D[i * kLd + j] = s;
+        {
+          dx4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int k0 = 0; k0 < kPC; k0 += 4) {
+            const int k = k0 + kq;
+            const double av = (brow < bj && k < bj && k >= brow)
+                                  ? (k == brow ? diag[brow] : G[k * kLd + brow])
+                                  : 0.0;
+            acc = mfma_f64(av, RB[k * kLd + 16 * bq + l16], acc);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) D[(16 * bp + kq + 4 * v) * kLd + 16 * bq + l16] = acc[v];
         }
         __syncthreads();                                         // G (R2) is overwritten next
         // Q11 into G, then its signed LU with U^{-1} in X and L^{-1} in RB
@@ -401,22 +412,20 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
         for (int e = t; e < kWords; e += kPanelThreads) publish(e5 + e, X[(e >> 6) * kLd + (e & 63)]);
         if (t < kPC) publish(e5 + kWords + t, t < bj ? sgn[t] : 0.0);
         // T = -U S L^{-T}: T[i][j] = -sum_{k=i..j} U[i][k] S[k] W[j][k]
-        double tv[kPC * kPC / kPanelThreads];
+        // (U: udiag and G's strict upper part; W = L^{-1} in RB, read transposed)
+        dx4 tacc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
-          const int e = t + q * kPanelThreads;
-          const int i = e >> 6, j = e & 63;
-          double s = 0.0;
-          if (i < bj && j < bj && i <= j)
-            for (int k = i; k <= j; ++k) s += (k == i ? udiag[i] : G[i * kLd + k]) * sgn[k] * RB[j * kLd + k];
-          tv[q] = -s;
+        for (int k0 = 0; k0 < kPC; k0 += 4) {
+          const int k = k0 + kq;
+          const double av = (brow < bj && k < bj && k >= brow)
+                                ? (k == brow ? udiag[brow] : G[brow * kLd + k]) * sgn[k]
+                                : 0.0;
+          const double bv = (k < bj) ? RB[(16 * bq + l16) * kLd + k] : 0.0;
+          tacc = mfma_f64(av, bv, tacc);
         }
-        __syncthreads();
+        __syncthreads();                                         // every wave is done with W
 #pragma unroll
-        for (int q = 0; q < kPC * kPC / kPanelThreads; ++q) {
-          const int e = t + q * kPanelThreads;
-          RB[(e >> 6) * kLd + (e & 63)] = tv[q];
-        }
+        for (int v = 0; v < 4; ++v) RB[(16 * bp + kq + 4 * v) * kLd + 16 * bq + l16] = -tacc[v];
         if (t < bj) {
           s_tau[t] = -udiag[t] * sgn[t];
           a.tau[t] = s_tau[t];
