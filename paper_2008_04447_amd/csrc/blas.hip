@@ -779,13 +779,13 @@ hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int
 // ---------------------------------------------------------------------------
 // permute: new X(:, q) = X(:, src_top[q]) for q < bj and
 // new X(:, dst_low[o]) = X(:, o) for o < bj with dst_low[o] >= 0 (positions
-// relative to the block start).  Each workgroup stages 64 rows of all moved
-// columns in LDS before writing, and workgroups own disjoint rows.
+// relative to the block start).  Each thread owns one row of a 64-row slab and
+// reads every moved value of that row into registers (all loads in flight at
+// once), then, after the workgroup's barrier, writes them: the only reads a
+// write could clobber are those of the same slab, and slabs are disjoint.
 __global__ __launch_bounds__(256) void permute_kernel(double* X, int64_t ldx, int rows, int bj,
                                                       const int* src_top, const int* dst_low,
                                                       int64_t* jpvt) {
-  __shared__ double s_top[64][65];
-  __shared__ double s_low[64][65];
   __shared__ int s_src[64], s_dst[64];
   const int t = threadIdx.x;
   if (t < 64) {
@@ -793,20 +793,23 @@ __global__ __launch_bounds__(256) void permute_kernel(double* X, int64_t ldx, in
     s_dst[t] = (t < bj) ? dst_low[t] : -1;
   }
   __syncthreads();
-  const int r0 = blockIdx.x * 64;
-  const int rr = t & 63;
-  const int r = r0 + rr;
-  for (int q = t >> 6; q < bj; q += 4) {
-    if (r < rows) {
-      s_top[q][rr] = X[r + (int64_t)s_src[q] * ldx];
-      s_low[q][rr] = (s_dst[q] >= 0) ? X[r + (int64_t)q * ldx] : 0.0;
-    }
+  const int r = blockIdx.x * 64 + (t & 63);
+  const bool rok = r < rows;
+  double top[16], low[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int q = (t >> 6) + 4 * i;
+    const bool qok = rok && q < bj;
+    top[i] = qok ? X[r + (int64_t)s_src[q] * ldx] : 0.0;
+    low[i] = (qok && s_dst[q] >= 0) ? X[r + (int64_t)q * ldx] : 0.0;
   }
   __syncthreads();
-  for (int q = t >> 6; q < bj; q += 4) {
-    if (r < rows) {
-      X[r + (int64_t)q * ldx] = s_top[q][rr];
-      if (s_dst[q] >= 0) X[r + (int64_t)s_dst[q] * ldx] = s_low[q][rr];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int q = (t >> 6) + 4 * i;
+    if (rok && q < bj) {
+      X[r + (int64_t)q * ldx] = top[i];
+      if (s_dst[q] >= 0) X[r + (int64_t)s_dst[q] * ldx] = low[i];
     }
   }
   if (jpvt && blockIdx.x == 0) {
