@@ -31,23 +31,39 @@ __global__ __launch_bounds__(256) void gemm_lx_narrow_kernel(GemmArgs g) {
 #pragma unroll
   for (int i = 0; i < PB; ++i) acc[i] = dx4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    double xb[4];
-    double la[PB][4];
+  // the chunk has at most 64 rows of K (four groups of 16): every operand, and
+  // the C values of the epilogue, is requested before the first product
+  double xb[4][4];
+  double la[4][PB][4];
+#pragma unroll
+  for (int c4 = 0; c4 < 4; ++c4) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int k = k0 + 4 * kq + s;
-      xb[s] = (nok && k < ke) ? xc[k] : 0.0;
+      const int k = kb + 16 * c4 + 4 * kq + s;
+      xb[c4][s] = (nok && k < ke) ? xc[k] : 0.0;
 #pragma unroll
       for (int i = 0; i < PB; ++i) {
         const int p = 16 * i + (lane & 15);
-        la[i][s] = (p < g.P && k < ke) ? g.L[(int64_t)p * g.sLp + (int64_t)k * g.sLk] : 0.0;
+        la[c4][i][s] = (p < g.P && k < ke) ? g.L[(int64_t)p * g.sLp + (int64_t)k * g.sLk] : 0.0;
       }
     }
+  }
+  const bool epi_c = g.ksplit == 1 && g.beta != 0.0 && nok;
+  double cv[PB][4];
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = 16 * i + kq + 4 * v;
+      cv[i][v] = (epi_c && p < g.P) ? g.C[p + (int64_t)n * g.ldc] : 0.0;
+    }
+#pragma unroll
+  for (int c4 = 0; c4 < 4; ++c4) {
+    if (kb + 16 * c4 >= ke) break;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int i = 0; i < PB; ++i) acc[i] = mfma_f64(la[i][s], xb[s], acc[i]);
+      for (int i = 0; i < PB; ++i) acc[i] = mfma_f64(la[c4][i][s], xb[c4][s], acc[i]);
   }
   if (!nok) return;
   if (g.ksplit > 1) {
@@ -67,7 +83,7 @@ __global__ __launch_bounds__(256) void gemm_lx_narrow_kernel(GemmArgs g) {
         const int p = 16 * i + kq + 4 * v;
         if (p < g.P) {
           double r = g.alpha * acc[i][v];
-          if (g.beta != 0.0) r += g.beta * g.C[p + (int64_t)n * g.ldc];
+          if (g.beta != 0.0) r += g.beta * cv[i][v];
           g.out[p + (int64_t)n * g.ldout] = r;
         }
       }
