@@ -488,22 +488,34 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
   __shared__ double s_T[64][65];   // s_T[q][i] = T(q, i), upper triangle
   __shared__ double s_Y[64][65];   // s_Y[r][i] = Y(r, i), r, i < bj
   __shared__ double s_v[4][64];
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+  const int i = threadIdx.x & 63;
+  const int cl = threadIdx.x >> 6;
+  // wave cl takes columns 16 blockIdx + 4 it + cl: their split-K partials and
+  // R12 entries are requested first, together with the staging of T and Y11
+  double w[4], r12[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int64_t n = (int64_t)blockIdx.x * 16 + 4 * it + cl;
+    const bool ok = n < N && i < bj;
+    double acc = 0.0;
+    if (ok)
+      for (int r = 0; r < ks; ++r) acc += part[r * sstride + i + n * 64];
+    w[it] = acc;
+    r12[it] = ok ? R12[i + n * ldr] : 0.0;
+  }
+#pragma unroll
+  for (int e0 = 0; e0 < 64 * 64; e0 += 256) {
+    const int e = e0 + threadIdx.x;
     const int a = e % 64, b = e / 64;
     s_T[a][b] = (a < bj && b < bj && a <= b) ? T[a + (int64_t)b * ldt] : 0.0;
     s_Y[a][b] = (a < bj && b < bj) ? Y[a + (int64_t)b * ldy] : 0.0;
   }
-  const int i = threadIdx.x & 63;
-  const int cl = threadIdx.x >> 6;
   __syncthreads();
-#pragma unroll 1
+#pragma unroll
   for (int it = 0; it < 4; ++it) {
     const int64_t n = (int64_t)blockIdx.x * 16 + 4 * it + cl;   // uniform per wave
     if (n >= N) break;
-    double w = 0.0;
-    if (i < bj)
-      for (int r = 0; r < ks; ++r) w += part[r * sstride + i + n * 64];
-    s_v[cl][i] = w;
+    s_v[cl][i] = w[it];
     // the wave's own LDS writes are visible to its later reads
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -511,18 +523,19 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
     double z = 0.0;
 #pragma unroll 16
     for (int q = 0; q < 64; ++q) z += s_T[q][i] * s_v[cl][q];
-    Z[i + n * 64] = (i < bj) ? z : 0.0;
+    z = (i < bj) ? z : 0.0;
+    Z[i + n * 64] = z;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    s_v[cl][i] = (i < bj) ? z : 0.0;
+    s_v[cl][i] = z;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double u = 0.0;
 #pragma unroll 16
     for (int q = 0; q < 64; ++q) u += s_Y[i][q] * s_v[cl][q];
-    if (i < bj) R12[i + n * ldr] -= u;
+    if (i < bj) R12[i + n * ldr] = r12[it] - u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
