@@ -1,9 +1,11 @@
 // Partial QRCP of the (b+p) x N sample (the pivot block of Algorithms 3-5).
 //
-// Each sample column is held in registers by a group of Q lanes (8, or 4 for
-// very wide samples) for the whole kernel: lane q of the group keeps rows q,
-// q+Q, q+2Q, ... (ell <= 96, padded with zero rows), 1024 / Q columns per
-// 1024-thread workgroup.  A pivot step needs the column of largest trailing
+// Each sample column is held in registers by a group of Q = 4 lanes for the
+// whole kernel: lane q of the group keeps rows q, q+4, q+8, ... (ell <= 96,
+// padded with zero rows); a workgroup of 512 threads holds 128 columns, or of
+// 1024 threads 256 columns for very wide samples (two waves per SIMD where
+// possible: the reflection is issue-bound, and four waves per SIMD would queue
+// behind each other on every step).  A pivot step needs the column of largest trailing
 // 2-norm over all workgroups, so every step has one cross-workgroup exchange:
 // each workgroup publishes a record for its best column (see the published
 // records in device_common.hpp) holding (norm^2, position, tau, beta) and the
@@ -23,13 +25,18 @@
 
 namespace rq {
 
-constexpr int kSqThreads = 1024;
-constexpr int kSqWaves = kSqThreads / 64;
 constexpr int kHead = 4;                        // record head: norm^2, position, tau, beta
-constexpr int kPollers = kSqThreads - 64;       // waves 1.. fetch the records
-constexpr int kPoll = 8;                        // record words one of them polls at most
-constexpr int kSpecCap = kPollers * kPoll;      // record words that fit the one-round fetch
 constexpr int kHeadPer = 4;                     // record heads one lane of wave 0 polls
+
+// Workgroup of NT threads: waves 1.. (NT - 64 threads) fetch the records, each
+// polling at most kPoll words; kSpecCap record words fit the one-round fetch.
+template <int NT>
+struct SqShape {
+  static constexpr int kWaves = NT / 64;
+  static constexpr int kPollers = NT - 64;
+  static constexpr int kPoll = NT >= 1024 ? 8 : 12;
+  static constexpr int kSpecCap = kPollers * kPoll;
+};
 static_assert(kHeadPer * 64 >= RQ_MAX_N / 256, "every workgroup's head is polled");
 
 // Sum over the Q lanes holding one column.
@@ -42,7 +49,9 @@ RQ_DEV double column_sum(double v) {
 
 // Waves 1..: wait until the words u, u + kPollers, ... (< total) of a step's
 // records are published, then copy them to s_all.  False when the wait gave up.
+template <int NT>
 RQ_DEV bool poll_records(const double* rj, int total, const SqArgs& a, int u, double* s_all) {
+  constexpr int kPoll = SqShape<NT>::kPoll, kPollers = SqShape<NT>::kPollers;
   unsigned long long b[kPoll];
 #pragma unroll
   for (int k = 0; k < kPoll; ++k) {
@@ -119,10 +128,12 @@ RQ_DEV bool poll_winner(const double* rj, const SqArgs& a, int lane, double& v, 
   return ok;
 }
 
-template <int LM, int Q>
-__global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
+template <int LM, int Q, int NT>
+__global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
   constexpr int kQ = Q;                        // lanes per column
-  constexpr int kSqCols = kSqThreads / kQ;     // columns per workgroup
+  constexpr int kSqCols = NT / kQ;             // columns per workgroup
+  constexpr int kSqWaves = SqShape<NT>::kWaves;
+  constexpr int kSpecCap = SqShape<NT>::kSpecCap;
   constexpr int RPL = LM / kQ;                 // rows per lane
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(kSqThreads) void sample_qrcp_kernel(SqArgs a) {
         s_hp[1] = ww;
       }
     } else if (spec) {
-      ok = poll_records(rj, a.nwg * a.rs, a, t - 64, s_all);
+      ok = poll_records<NT>(rj, a.nwg * a.rs, a, t - 64, s_all);
     }
     if (__syncthreads_or(!ok)) return;
     const int wpos = s_hp[0];
@@ -334,9 +345,9 @@ static hipError_t launch_lm(const SqArgs& a, hipStream_t s) {
   const bool wide = (int64_t)a.nwg * 128 >= a.N;
   if (a.nwg < 1 || (int64_t)a.nwg * 256 < a.N) return hipErrorInvalidValue;
   if (wide)
-    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 8>), dim3(a.nwg), dim3(kSqThreads), 0, s, a);
+    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4, 512>), dim3(a.nwg), dim3(512), 0, s, a);
   else
-    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4>), dim3(a.nwg), dim3(kSqThreads), 0, s, a);
+    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4, 1024>), dim3(a.nwg), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
