@@ -202,21 +202,26 @@ RQ_DEV dx4 gram_chunk(const double* X, dx4 acc, int p, int q, int lane) {
   }
   return acc;
 }
-// Product of a 64-row chunk X with a 64 x 64 matrix B (both LDS, row-major).
+// Product of a 64-row chunk X with an upper-triangular 64 x 64 matrix B (both
+// LDS, row-major): column block q of the result needs rows k < 16 (q + 1) of B
+// only.
 RQ_DEV dx4 product_chunk(const double* X, const double* B, int p, int q, int lane) {
   dx4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int kend = 16 * (q + 1);
 #pragma unroll
   for (int k0 = 0; k0 < kPC; k0 += 4) {
-    const double a = X[(16 * p + (lane & 15)) * kLd + k0 + (lane >> 4)];
-    const double b = B[(k0 + (lane >> 4)) * kLd + 16 * q + (lane & 15)];
-    acc = mfma_f64(a, b, acc);
+    if (k0 < kend) {
+      const double a = X[(16 * p + (lane & 15)) * kLd + k0 + (lane >> 4)];
+      const double b = B[(k0 + (lane >> 4)) * kLd + 16 * q + (lane & 15)];
+      acc = mfma_f64(a, b, acc);
+    }
   }
   return acc;
 }
 
 // x <- x B for this workgroup's 256 x 64 tile (held as x[i] = row g + 16 i of
-// column c), staged through X in four chunks of 64 rows.  Rows of the panel
-// below `keep_below` (global index) keep their values.
+// column c) and an upper-triangular B, staged through X in four chunks of 64
+// rows.  Rows of the panel below `keep_below` (global index) keep their values.
 RQ_DEV void tile_times(double (&x)[kPR], double* X, const double* B, int t, int rbase,
                        int keep_below) {
   const int g = t % kPG, c = t / kPG, lane = t & 63, wave = t >> 6;
@@ -360,7 +365,21 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
           em = (v > em || v != v) ? v : em;
         }
       }
-      if (!__syncthreads_or(!(em <= 1e-10))) {
+      // Within 64 eps of the identity, Q1 is already orthonormal to working
+      // precision: Q = Q1 and R = R1 (R2 taken as I, its product skipped).
+      const bool ident = !__syncthreads_or(!(em <= 64.0 * 2.220446049250313e-16));
+      if (ident) {
+        for (int e = t; e < kPC * kLd; e += kPanelThreads) {
+          const int i = e / kLd, j = e - i * kLd;
+          if (i < bj && j < bj) {
+            if (i == j)
+              diag[i] = 1.0;
+            else if (i < j)
+              G[j * kLd + i] = 0.0;
+          }
+        }
+        __syncthreads();
+      } else if (!__syncthreads_or(!(em <= 1e-10))) {
         // R2 transposed into G's lower part and its diagonal into diag, as the
         // sweep leaves them; D = R2^{-1} (upper)
         for (int e = t; e < kPC * kLd; e += kPanelThreads) {
@@ -382,7 +401,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
       } else if (!chol_inv(G, D, diag, bj, t) && t == 0) {
         raise_status(a.status, kErrNonFinite);
       }
-      tile_times(x, X, D, t, rbase, 0);                          // Q = Q1 R2^{-1}
+      if (!ident) tile_times(x, X, D, t, rbase, 0);              // Q = Q1 R2^{-1}
       if (wg == 0) {
         // the 16 x 16 block (bp, bq) of a 64 x 64 product per wave, on the
         // matrix cores; lane holds rows 16 bp + kq + 4 v, column 16 bq + l16
