@@ -487,21 +487,23 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
                                                            double* R12, int64_t ldr, int bj) {
   __shared__ double s_T[64][65];   // s_T[q][i] = T(q, i), upper triangle
   __shared__ double s_Y[64][65];   // s_Y[r][i] = Y(r, i), r, i < bj
-  __shared__ double s_v[4][64];
+  __shared__ double s_v[4][64][4]; // per wave: the 4 columns' vectors, row-major [q][c]
   const int i = threadIdx.x & 63;
   const int cl = threadIdx.x >> 6;
-  // wave cl takes columns 16 blockIdx + 4 it + cl: their split-K partials and
-  // R12 entries are requested first, together with the staging of T and Y11
+  // wave cl takes the 4 columns 16 blockIdx + 4 cl + c together, so that every
+  // T and Y11 entry read from LDS feeds four products; their split-K partials
+  // and R12 entries are requested first, with the staging of T and Y11
+  const int64_t n0 = (int64_t)blockIdx.x * 16 + 4 * cl;
   double w[4], r12[4];
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int64_t n = (int64_t)blockIdx.x * 16 + 4 * it + cl;
+  for (int c = 0; c < 4; ++c) {
+    const int64_t n = n0 + c;
     const bool ok = n < N && i < bj;
     double acc = 0.0;
     if (ok)
       for (int r = 0; r < ks; ++r) acc += part[r * sstride + i + n * 64];
-    w[it] = acc;
-    r12[it] = ok ? R12[i + n * ldr] : 0.0;
+    w[c] = acc;
+    r12[c] = ok ? R12[i + n * ldr] : 0.0;
   }
 #pragma unroll
   for (int e0 = 0; e0 < 64 * 64; e0 += 256) {
@@ -510,36 +512,42 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
     s_T[a][b] = (a < bj && b < bj && a <= b) ? T[a + (int64_t)b * ldt] : 0.0;
     s_Y[a][b] = (a < bj && b < bj) ? Y[a + (int64_t)b * ldy] : 0.0;
   }
-  __syncthreads();
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int64_t n = (int64_t)blockIdx.x * 16 + 4 * it + cl;   // uniform per wave
-    if (n >= N) break;
-    s_v[cl][i] = w[it];
-    // the wave's own LDS writes are visible to its later reads
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double z = 0.0;
-#pragma unroll 16
-    for (int q = 0; q < 64; ++q) z += s_T[q][i] * s_v[cl][q];
-    z = (i < bj) ? z : 0.0;
-    Z[i + n * 64] = z;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    s_v[cl][i] = z;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double u = 0.0;
-#pragma unroll 16
-    for (int q = 0; q < 64; ++q) u += s_Y[i][q] * s_v[cl][q];
-    if (i < bj) R12[i + n * ldr] = r12[it] - u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int c = 0; c < 4; ++c) s_v[cl][i][c] = w[c];
+  __syncthreads();
+  // Z(:, n) = T^T W(:, n)
+  double z[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int q = 0; q < 64; ++q) {
+    const double tq = s_T[q][i];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) z[c] += tq * s_v[cl][q][c];
   }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    z[c] = (i < bj) ? z[c] : 0.0;
+    if (n0 + c < N) Z[i + (n0 + c) * 64] = z[c];
+  }
+  // the wave's own LDS accesses complete in order
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s_v[cl][i][c] = z[c];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // R12(:, n) -= Y11 Z(:, n)
+  double u[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int q = 0; q < 64; ++q) {
+    const double yq = s_Y[i][q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] += yq * s_v[cl][q][c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (n0 + c < N && i < bj) R12[i + (n0 + c) * ldr] = r12[c] - u[c];
 }
 
 hipError_t launch_reduce_r12(const double* part, int64_t sstride, int ks, int N, double* Z,
