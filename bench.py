@@ -29,8 +29,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64_tflops": 78.6, "hbm_gbs": 8000.0}
-MFMA_CLASSES = {"sketch", "inner_products", "trailing_update", "sample_update", "qp3_gemv"}
+PEAK = {"fp64_tflops": 78.6, "bf16_tflops": 2500.0, "hbm_gbs": 8000.0}
+MFMA_CLASSES = {"sketch", "inner_products", "trailing_update", "sample_update", "qp3_gemv",
+                "sketch_bf16", "inner_products_bf16"}
 
 
 def log(msg):
@@ -136,12 +137,17 @@ def measured_traffic(workload, cls):
 
 
 def roofline(prof, steps, workload=None):
-    """Roofline entry of the kernel class with the largest total time."""
+    """Roofline entry of the kernel class with the largest total time.  A
+    contraction class is MFMA-bound when its algorithmic flops per byte reach
+    the ridge of its dtype (peak flops / HBM bandwidth), else HBM-bound."""
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     sec = rec["ms"] * 1e-3
-    if name in MFMA_CLASSES:
+    fpeak = PEAK["bf16_tflops" if name.endswith("_bf16") else "fp64_tflops"]
+    mfma = name in MFMA_CLASSES and (rec["bytes"] <= 0 or
+                                     rec["flops"] / rec["bytes"] * PEAK["hbm_gbs"] * 1e-3 >= fpeak)
+    if mfma:
         achieved = rec["flops"] / sec / 1e12
-        peak = PEAK["fp64_tflops"]
+        peak = fpeak
         bound, unit = "mfma", "TFLOP/s"
     else:
         achieved = rec["bytes"] / sec / 1e9

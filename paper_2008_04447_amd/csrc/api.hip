@@ -156,7 +156,7 @@ rq_status sketch_bf16(rq_handle h, int ell, int64_t m, int64_t n, const double* 
   g.P = ell;
   g.K = (int)m;
   g.N = (int)n;
-  return gemm_lx_bf16_reduced(h, K_SKETCH, g, part, B, ldb, lbf);
+  return gemm_lx_bf16_reduced(h, K_SKETCH_BF16, g, part, B, ldb, lbf);
 }
 
 size_t sq_rec_doubles(int ell, int64_t N) {

@@ -4,7 +4,8 @@
 //   * gemm_lx_bf16 : D(P x N) = L(P x K) X(K x N), X an FP32 matrix read through
 //                    an optional column map (the sketch Omega A and Y2^T A P);
 //                    L is staged once per launch as BF16 in a workspace;
-//   * gemm_nn_bf16 : C(M x N) = Y(M x K) Z(K x N), Y FP32 (Z1 = A V of TUXV).
+//   * gemm_nn_bf16 : C(M x N) = Y(M x K) Z(K x N), Y FP32 (Z1 = A V of TUXV);
+//                    Z is staged once as BF16 in a workspace.
 // v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) + e] and
 // B[8 (l / 16) + e][l % 16] (e = 0..7) and holds D[4 (l / 16) + i][l % 16].
 #include "device_common.hpp"
@@ -13,6 +14,7 @@
 namespace rq {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
 
 RQ_DEV fx4 mfma_bf16(bf16x8 a, bf16x8 b, fx4 c) {
@@ -162,62 +164,229 @@ hipError_t launch_gemm_lx_bf16(const GemmArgsF& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// C(M x N) = Y(M x K) Z(K x N): 64 x 64 tile per workgroup, wave (wr, wc) owns
-// 32 x 32 as 2 x 2 blocks of C^T (so 16 lanes store 16 consecutive rows).
-__global__ __launch_bounds__(256) void gemm_nn_bf16_kernel(double* C, int64_t ldc, int M, int N,
-                                                          const float* Y, int64_t ldy,
-                                                          const double* Z, int64_t ldz, int K) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int rb = blockIdx.x * 64 + (wave & 1) * 32;
-  const int cb = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int l16 = lane & 15;
-  const int kq = lane >> 4;
-  fx4 acc[2][2];
+// ---- C(M x N) = Y(M x K) Z(K x N) ----------------------------------------
+// The one extra pass over A in TUXV (Z1 = A V): Y is the FP32 input, column-major,
+// so its rows are contiguous and a 64-row tile of one column is 256 bytes.
+//   * Z is staged once as BF16, step-major: the 64 k of step s for all ncp
+//     padded columns form one contiguous block, so the slab every workgroup
+//     needs at step s is 64 ncp consecutive values (cache- and TLB-friendly).
+//   * A workgroup owns 64 rows of C and 64 NBW columns (all of N when N <= 256),
+//     so Y is read once.  Per 64-k step its 256 threads load the 64 x 64 Y tile
+//     with float4 loads along rows (4 rows x 4 columns per thread), round it to
+//     BF16 and store it to LDS row-major (k contiguous), from which each lane
+//     reads the 8 consecutive k of one row an MFMA operand needs.
+//   * Wave w owns columns 16 NBW w ..; its Z fragments come straight from the
+//     staged array.  Loads run ahead of use: the Y tile of step s + 2 is issued
+//     during step s (two register sets), and each half-step's Z fragments are
+//     replaced by the next step's as soon as they are consumed, Z before Y so
+//     that waiting for Z never waits for the later Y tile.
+//   * Rows at or past M in the last tile are clamped to valid rows and their
+//     results dropped; columns past K (the K tail) are zero.
+// Products run in the same order as a plain k-ordered loop of 16x16x32 MFMAs.
+constexpr int kNnRows = 64;   // rows of C per workgroup
+constexpr int kNnK = 64;      // k per pipeline step
+constexpr int kNnLd = 72;     // LDS row stride of the BF16 Y tile (elements; 144 bytes)
+
+static int nn_nbw(int N) { return N > 192 ? 4 : N > 128 ? 3 : N > 64 ? 2 : 1; }
+static int nn_ncp(int N) {
+  const int cols = 64 * nn_nbw(N);
+  return ((N + cols - 1) / cols) * cols;
+}
+int64_t gemm_nn_bf16_stage_elems(int N, int K) {
+  return (int64_t)nn_ncp(N) * (((K + kNnK - 1) / kNnK) * kNnK);
+}
+
+// Z (K x N, FP64) through FP32 to BF16: element (k, c) at
+// ((k / 64) ncp + c) 64 + k % 64, zero for c >= N or k >= K.
+__global__ void stage_z_bf16_kernel(const double* Z, int64_t ldz, int N, int K, int ncp, int64_t total,
+                                    __bf16* zt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int kk = (int)(e & 63);
+  const int64_t sc = e >> 6;
+  const int c = (int)(sc % ncp);
+  const int k = (int)(sc / ncp) * kNnK + kk;
+  zt[e] = (__bf16)(float)((c < N && k < K) ? Z[k + (int64_t)c * ldz] : 0.0);
+}
+
+// The K loop of one workgroup.  VEC: Y 16-byte aligned, ldy and M multiples of 4
+// and ldy < 2^26 (32-bit lane offsets); otherwise element loads.
+template <int NBW, bool VEC>
+RQ_DEV void nn_tile(fx4 (&acc)[4][NBW], __bf16 (*s_y)[kNnRows * kNnLd], int M, const float* Y,
+                    int64_t ldy, const __bf16* zt, int ncp, int K, int r0, int cw) {
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int rg = t & 15, kc = t >> 4;   // loader: rows 4 rg .. 4 rg + 3, columns 4 kc .. 4 kc + 3
+  // wave-uniform bases plus per-lane offsets
+  const float* yw = Y + r0;
+  const uint32_t yoff = (uint32_t)min(4 * rg, M - 4 - r0) + (uint32_t)(4 * kc) * (uint32_t)ldy;
+  int64_t yoq[4];
 #pragma unroll
-  for (int ib = 0; ib < 2; ++ib)
+  for (int q = 0; q < 4; ++q) yoq[q] = min(4 * rg + q, M - 1 - r0) + (int64_t)(4 * kc) * ldy;
+  const __bf16* zw = zt + (int64_t)cw * kNnK;
+  const uint32_t zoff = (uint32_t)(l16 * kNnK + 8 * kq);
+  const int nsteps = (K + kNnK - 1) / kNnK;
+  const int nfull = K / kNnK;   // steps whose 64 columns are all below K
+
+  auto load_y = [&](fx4 (&u)[4], int s) {
+    const float* p = yw + (int64_t)(s * kNnK) * ldy;
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = fx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const int kk = k0 + 8 * kq;
-    bf16x8 za[2], yb[2];
+    for (int e = 0; e < 4; ++e) {
+      const float* pe = p + (int64_t)e * ldy;
+      if (VEC) {
+        u[e] = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(pe + yoff));
+      } else {
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      const int cc = cb + 16 * jb + l16;
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        za[jb][e] = (__bf16)(float)((cc < N && kk + e < K) ? Z[(kk + e) + (int64_t)cc * ldz] : 0.0);
-    }
-#pragma unroll
-    for (int ib = 0; ib < 2; ++ib) {
-      const int r = rb + 16 * ib + l16;
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        yb[ib][e] = (__bf16)((r < M && kk + e < K) ? Y[r + (int64_t)(kk + e) * ldy] : 0.f);
-    }
-#pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-      for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = mfma_bf16(za[jb], yb[ib], acc[ib][jb]);
-  }
-#pragma unroll
-  for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      const int r = rb + 16 * ib + l16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int cc = cb + 16 * jb + 4 * kq + v;
-        if (r < M && cc < N) C[r + (int64_t)cc * ldc] = (double)acc[ib][jb][v];
+        for (int q = 0; q < 4; ++q) u[e][q] = __builtin_nontemporal_load(pe + yoq[q]);
       }
     }
+  };
+  auto load_y_tail = [&](fx4 (&u)[4], int s) {
+    const int k0 = s * kNnK;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float* pe = yw + (int64_t)(k0 + e) * ldy;
+      const bool ok = k0 + 4 * kc + e < K;
+      if (VEC) {
+        u[e] = ok ? *reinterpret_cast<const fx4*>(pe + yoff) : fx4{0.f, 0.f, 0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[e][q] = ok ? pe[yoq[q]] : 0.f;
+      }
+    }
+  };
+  auto zfrag = [&](int s, int h, int jb) {
+    return *reinterpret_cast<const bf16x8*>((zw + ((int64_t)s * ncp + 16 * jb) * kNnK + 32 * h) + zoff);
+  };
+  auto store_y = [&](__bf16* buf, const fx4 (&u)[4]) {
+    __bf16* p = buf + (4 * rg) * kNnLd + 4 * kc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<bf16x4*>(p + q * kNnLd) =
+          bf16x4{(__bf16)u[0][q], (__bf16)u[1][q], (__bf16)u[2][q], (__bf16)u[3][q]};
+  };
+  // MFMAs of one step from the LDS tile and the fragments in z; each half's
+  // fragments are then replaced by those of step snext (always a valid step).
+  auto compute = [&](const __bf16* buf, bf16x8 (&z)[2][NBW], int snext) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf16x8 yf[4];
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib)
+        yf[ib] = *reinterpret_cast<const bf16x8*>(buf + (16 * ib + l16) * kNnLd + 32 * h + 8 * kq);
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = mfma_bf16(z[h][jb], yf[ib], acc[ib][jb]);
+#pragma unroll
+      for (int jb = 0; jb < NBW; ++jb) z[h][jb] = zfrag(snext, h, jb);
+    }
+  };
+  if (nsteps == 0) return;
+  const int last = nsteps - 1;
+  fx4 ya[4], yb[4];
+  bf16x8 z[2][NBW];
+  auto load_z0 = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int jb = 0; jb < NBW; ++jb) z[h][jb] = zfrag(0, h, jb);
+  };
+  if (nfull > 0) {
+    // Full steps without branches around loads: a prefetch past the last full
+    // step reloads that step (in range, unused), so the compiler's waits are
+    // plain in-order counts.  The prologue issues loads in the loop's order.
+    const int lf = nfull - 1;
+    load_y(ya, 0);
+    load_z0();
+    load_y(yb, min(1, lf));
+    int s = 0;
+#pragma unroll 1
+    for (; s + 1 < nfull; s += 2) {
+      store_y(s_y[0], ya);
+      __syncthreads();
+      compute(s_y[0], z, s + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      load_y(ya, min(s + 2, lf));
+      store_y(s_y[1], yb);
+      __syncthreads();
+      compute(s_y[1], z, min(s + 2, last));
+      __builtin_amdgcn_sched_barrier(0);
+      load_y(yb, min(s + 3, lf));
+    }
+    if (s < nfull) {   // odd number of full steps: the last one is in ya
+      store_y(s_y[0], ya);
+      __syncthreads();
+      compute(s_y[0], z, min(s + 1, last));
+    }
+  } else {
+    load_z0();
+  }
+  if (nfull < nsteps) {   // K tail (z already holds this step)
+    load_y_tail(ya, nfull);
+    __syncthreads();
+    store_y(s_y[0], ya);
+    __syncthreads();
+    compute(s_y[0], z, last);
+  }
+}
+
+template <int NBW>
+__global__ __launch_bounds__(256, 2) void gemm_nn_bf16_kernel(double* C, int64_t ldc, int M, int N,
+                                                              const float* Y, int64_t ldy,
+                                                              const __bf16* zt, int ncp, int K,
+                                                              int vec) {
+  __shared__ __align__(16) __bf16 s_y[2][kNnRows * kNnLd];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int r0 = blockIdx.x * kNnRows;
+  const int cw = blockIdx.y * 64 * NBW + 16 * NBW * wave;
+  fx4 acc[4][NBW];
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = fx4{0.f, 0.f, 0.f, 0.f};
+  if (vec)
+    nn_tile<NBW, true>(acc, s_y, M, Y, ldy, zt, ncp, K, r0, cw);
+  else
+    nn_tile<NBW, false>(acc, s_y, M, Y, ldy, zt, ncp, K, r0, cw);
+  // lane holds C(r0 + 16 ib + l16, cw + 16 jb + 4 kq + v)
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib) {
+    const int r = r0 + 16 * ib + l16;
+#pragma unroll
+    for (int jb = 0; jb < NBW; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cc = cw + 16 * jb + 4 * kq + v;
+        if (r < M && cc < N) C[r + (int64_t)cc * ldc] = (double)acc[ib][jb][v];
+      }
+  }
 }
 
 hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float* Y, int64_t ldy,
-                               const double* Z, int64_t ldz, int K, hipStream_t s) {
+                               const double* Z, int64_t ldz, int K, __bf16* zbf, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid((M + 63) / 64, (N + 63) / 64);
-  hipLaunchKernelGGL(gemm_nn_bf16_kernel, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, Z, ldz, K);
+  if (ldy < M || ldc < M || (K > 0 && !zbf)) return hipErrorInvalidValue;
+  const int nbw = nn_nbw(N), ncp = nn_ncp(N);
+  const int64_t total = gemm_nn_bf16_stage_elems(N, K);
+  if (total > 0) {
+    hipLaunchKernelGGL(stage_z_bf16_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Z,
+                       ldz, N, K, ncp, total, zbf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int vec = (reinterpret_cast<uintptr_t>(Y) % 16 == 0) && (ldy % 4 == 0) && (M % 4 == 0) &&
+                  ldy < (1 << 26);
+  dim3 grid((M + kNnRows - 1) / kNnRows, ncp / (64 * nbw));
+  switch (nbw) {
+    case 1: hipLaunchKernelGGL(gemm_nn_bf16_kernel<1>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
+    case 2: hipLaunchKernelGGL(gemm_nn_bf16_kernel<2>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
+    case 3: hipLaunchKernelGGL(gemm_nn_bf16_kernel<3>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
+    default: hipLaunchKernelGGL(gemm_nn_bf16_kernel<4>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
+  }
   return hipGetLastError();
 }
 

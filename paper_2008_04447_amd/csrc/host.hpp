@@ -29,6 +29,8 @@ enum KClass {
   K_TR_ROWS,        // TRQRCP: new R rows A - Y W^T
   K_TR_SMALL,       // TRQRCP/TUXV: small products (Y2^T Y, T composition, ...)
   K_OTHER,
+  K_SKETCH_BF16,    // mixed precision: B = Omega A with BF16 operands
+  K_INNER_BF16,     // mixed precision: products over A with BF16 operands
   K_NUM_CLASSES
 };
 
@@ -36,7 +38,7 @@ inline const char* kclass_name(int c) {
   static const char* names[K_NUM_CLASSES] = {
       "sketch", "sample_qrcp", "permute", "panel", "inner_products", "reduce",
       "trailing_update", "omega11", "sample_update", "qp3_pivot", "qp3_gemv", "qp3_row",
-      "tr_select", "tr_rows", "tr_small", "other"};
+      "tr_select", "tr_rows", "tr_small", "other", "sketch_bf16", "inner_products_bf16"};
   return (c >= 0 && c < K_NUM_CLASSES) ? names[c] : "?";
 }
 

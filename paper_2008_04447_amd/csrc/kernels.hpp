@@ -80,9 +80,12 @@ int bf16_stage_kpad(int K);
 inline int64_t bf16_stage_elems(int64_t K) { return (int64_t)96 * (((K + 31) / 32) * 32 + 32); }
 // Stages L as BF16 into g.lbf, then runs the contraction (two kernels on stream s).
 hipError_t launch_gemm_lx_bf16(const GemmArgsF& g, hipStream_t s);
-// C(M x N) = Y(M x K) Z(K x N) with Y FP32 and Z FP64, both rounded to BF16.
+// C(M x N) = Y(M x K) Z(K x N) with Y FP32 and Z FP64, both rounded to BF16
+// (ldy, ldc >= M).  Z is first staged into zbf, which holds at least
+// gemm_nn_bf16_stage_elems(N, K) BF16 values (two kernels on stream s).
+int64_t gemm_nn_bf16_stage_elems(int N, int K);
 hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float* Y, int64_t ldy,
-                               const double* Z, int64_t ldz, int K, hipStream_t s);
+                               const double* Z, int64_t ldz, int K, __bf16* zbf, hipStream_t s);
 
 // sum of split-K partials; with T != null the result is Z = T^T W written with
 // leading dimension ldz = 64 (rows bj..63 zero) -- the trailing-update operand.

@@ -179,7 +179,7 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
         g.P = bj;
         g.K = (int)M;
         g.N = (int)Nt;
-        RQ_TRY(gemm_lx_bf16_reduced(h, K_INNER, g, w.part, w.sbuf, 64, w.lbf));
+        RQ_TRY(gemm_lx_bf16_reduced(h, K_INNER_BF16, g, w.part, w.sbuf, 64, w.lbf));
       } else {
         GemmArgs g{};
         g.L = w.ybuf;
@@ -326,12 +326,18 @@ static rq_status form_q(rq_handle h, const double* A, int64_t lda, int64_t M, in
   return RQ_OK;
 }
 
+// TUXV state beside the TRQRCP work: Y, T, R, Z0^T, Z1, two T stacks, tau and
+// the BF16 staging of V (carved in this order by tuxv_svd).
+static size_t tuxv_extra_bytes(int64_t m, int64_t n, int64_t k) {
+  return padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) + padded_bytes((size_t)k * n) +
+         padded_bytes((size_t)n * k) + padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
+         padded_bytes((size_t)k + 64) +
+         padded_bytes((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4);
+}
+
 size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv) {
   size_t w = trwork_doubles(m, n, k, ell);
-  if (tuxv)
-    w += padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) + padded_bytes((size_t)k * n) +
-         padded_bytes((size_t)n * k) + padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
-         padded_bytes((size_t)k + 64);
+  if (tuxv) w += tuxv_extra_bytes(m, n, k);
   return w;
 }
 
@@ -402,10 +408,7 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   DeviceGuard guard(h->device);
   const int ell = (int)(b + p);
   // TRQRCP state (Y, T, R) plus the two QR work arrays live in the workspace.
-  const size_t extra = padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) +
-                       padded_bytes((size_t)k * n) + padded_bytes((size_t)n * k) +
-                       padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
-                       padded_bytes((size_t)k + 64);
+  const size_t extra = tuxv_extra_bytes(m, n, k);
   RQ_TRY(reserve(h, trwork_doubles(m, n, k, ell) + extra));
   Carve cv(h->ws);
   TrWork w = carve_trwork(cv, m, n, k, ell);
@@ -417,6 +420,8 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   double* Tb = cv.take<double>((size_t)64 * k);
   double* Tb2 = cv.take<double>((size_t)64 * k);
   double* tauq = cv.take<double>((size_t)k + 64);
+  __bf16* vbf = reinterpret_cast<__bf16*>(
+      cv.take<double>((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4));   // V as BF16
   const bool f32 = prec == RQ_MIXED_BF16;
   hipStream_t s = h->stream;
   // 1. TRQRCP: A P ~ Q R
@@ -431,10 +436,12 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   RQ_TRY(form_q(h, Z0T, n, n, k, Tb, V, ldv, w));
   // 4. Z1 = A V (the one extra pass over A)
   {
-    KTimer kt(h, K_INNER, 2.0 * (double)m * n * k, 8.0 * ((double)m * n + (double)n * k + (double)m * k));
+    // algorithmic bytes: A once (FP32 or FP64), V and Z1 in FP64
+    KTimer kt(h, f32 ? K_INNER_BF16 : K_INNER, 2.0 * (double)m * n * k,
+              (f32 ? 4.0 : 8.0) * (double)m * n + 8.0 * ((double)n * k + (double)m * k));
     if (f32)
       RQ_CHECK(h, launch_gemm_nn_bf16(Z1, m, (int)m, (int)k, static_cast<const float*>(A), lda, V,
-                                      ldv, (int)n, s));
+                                      ldv, (int)n, vbf, s));
     else
       RQ_CHECK(h, launch_gemm_nn(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda, V, ldv,
                                  (int)n, 1.0, 0.0, s));
