@@ -82,107 +82,257 @@ RQ_DEV bool wait_words(Src src, int total, Put put, int t, uint32_t* abort_flag,
   return ok;
 }
 
-// Cholesky G = R^T R of the leading n x n block and R^{-1}, all threads of the
-// workgroup, one barrier per column.  On entry A holds G (upper part read); on
-// exit R's strict upper part is stored transposed in A's strict lower part
-// (A[j][k] = R[k][j], j > k), its diagonal in diag[], and Minv holds R^{-1}
-// (upper, zero elsewhere).  Column k of R^{-1} follows from the columns before
-// it: Minv[i][k] = -(sum_{l=i}^{k-1} Minv[i][l] R[l][k]) / R[k][k].  Returns
-// false when a pivot is not positive or not finite (same value in all threads).
+// The two 64 x 64 factorizations of the Cholesky-QR route, blocked by four
+// columns per workgroup barrier.
+// Wave w keeps rows 4w..4w+3 in registers for the whole factorization (lane =
+// column).  A block step applies the four column updates of the current block
+// to every row below it, each element taking them one after the other in the
+// sweep's order, with the block rows read once from LDS and the entries of a
+// wave's own columns taken by readlane; the wave owning the next four rows then
+// eliminates them among themselves and writes them to LDS, final, while the
+// waves above compute the block's four columns of the triangular inverses.
+// Every entry sees the same operations in the same order as in the sweeps, so
+// the results are those of the one-column-per-step sweeps; each row is
+// written once.
+
+// Cholesky G = R^T R of the leading n x n block and R^{-1}.  On entry A holds G
+// (upper part read); on exit R's strict upper part is stored transposed in A's
+// strict lower part (A[j][k] = R[k][j], j > k), its diagonal in diag[], and
+// Minv holds R^{-1} (upper, zero elsewhere):
+// Minv[i][k] = -(sum_{l=i}^{k-1} Minv[i][l] R[l][k]) / R[k][k].  1 / R[k][k] is
+// kept past Minv's 64 rows.  Returns false when a pivot is not positive or not
+// finite (same value in all threads).
 RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
+  const int lane = t & 63, wave = t >> 6;
   const int g = t & 15, row = t >> 4;
-  const int lane = t & 63, wave = t >> 6;     // wave w owns rows 4w..4w+3 of both parts
+  double* const rv = Minv + kPC * kLd;
   for (int e = t; e < kPC * kLd; e += kPanelThreads) Minv[e] = 0.0;
-  __syncthreads();
+  double a[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) a[q] = A[(4 * wave + q) * kLd + lane];
   bool ok = true;
-  for (int k = 0; k < n; ++k) {
-    const double d = A[k * kLd + k];
-    ok = ok && (d > 0.0) && (d < 1.7976931348623157e308);
-    const double rinv = rsqrt_nr(d);
-    const double rkk = d * rinv;
-    const double dinv = rinv * rinv;
-    // trailing update of the upper part: A[i][j] -= A[k][i] A[k][j] / d, k < i <= j < n,
-    // lane = column j; waves whose rows are all <= k issue nothing
-    if (4 * wave + 3 > k) {
-      const double ckj = A[k * kLd + lane] * dinv;
+  __syncthreads();
+  // the calling wave's rows k1..k1+3 among themselves, then stored
+  auto block_rows = [&](int k1) {
+    double blk[4][4];
+#pragma unroll
+    for (int c1 = 0; c1 < 4; ++c1)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) blk[c1][c] = (c1 <= c) ? readlane_f64(a[c1], k1 + c) : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = k1 + c;
+      if (k >= n) break;
+      const double d = blk[c][c];
+      ok = ok && (d > 0.0) && (d < 1.7976931348623157e308);
+      const double rinv = rsqrt_nr(d);
+      const double dinv = rinv * rinv;
+      if (lane == 0) {
+        diag[k] = d * rinv;
+        rv[k] = rinv;
+      }
+      if (lane > k && lane < n) A[lane * kLd + k] = a[c] * rinv;   // row k of R, transposed
+      const double ckj = a[c] * dinv;
+#pragma unroll
+      for (int c2 = c + 1; c2 < 4; ++c2) {
+        if (k1 + c2 <= lane && lane < n) a[c2] -= blk[c][c2] * ckj;
+#pragma unroll
+        for (int c3 = c2; c3 < 4; ++c3) blk[c2][c3] -= blk[c][c2] * (blk[c][c3] * dinv);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k1 + q < n && k1 + q <= lane && lane < n) A[(k1 + q) * kLd + lane] = a[q];
+  };
+  if (wave == 0) block_rows(0);
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    // the wave owning the next block is on the critical path: it goes first
+    const bool owner = wave == k0 / 4 + 1 && k0 + 4 < n;
+    if (owner) __builtin_amdgcn_s_setprio(3);
+    // rows below the block: A[i][j] -= A[k][i] A[k][j] / d, k = k0..k0+3, i <= j
+    if (4 * wave >= k0 + 4 && 4 * wave < n) {
+      double ak[4], dv[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = min(k0 + c, n - 1);
+        ak[c] = A[k * kLd + lane];
+        dv[c] = rv[k] * rv[k];
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * wave + q;
-        if (i > k && lane >= i && lane < n) A[i * kLd + lane] -= A[k * kLd + i] * ckj;
+        if (i >= n) break;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (k0 + c >= n) break;
+          const double aki = readlane_f64(ak[c], i);
+          if (lane >= i && lane < n) a[q] -= aki * (ak[c] * dv[c]);
+        }
       }
     }
-    // row k of R, stored transposed below the diagonal
-    if (t > k && t < n) A[t * kLd + k] = A[k * kLd + t] * rinv;
-    if (t == 0) diag[k] = rkk;
-    // column k of R^{-1}: 16 lanes per row (rows beyond k issue nothing)
-    if (4 * wave <= k) {
-      double acc = 0.0;
-      for (int l = row + g; l < k; l += 16) acc += Minv[row * kLd + l] * A[k * kLd + l];
-      acc = row16_sum(acc);
-      if (g == 0) {
-        if (row < k)
-          Minv[row * kLd + k] = -acc * rinv;
-        else if (row == k)
-          Minv[k * kLd + k] = rinv;
+    if (owner) {
+      block_rows(k0 + 4);
+      __builtin_amdgcn_s_setprio(0);
+    }
+    // columns k0..k0+3 of R^{-1} (rows up to k0 + 3).  A lane's terms of the
+    // dot products sit at l = row + g + 16 m, so at most one falls inside the
+    // block: the four partial sums over l < k0 are formed first, and each
+    // column then adds that one term from the block values kept in registers.
+    if (row <= k0 + 3) {
+      double P[4] = {0.0, 0.0, 0.0, 0.0};
+      int l = row + g;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (l < k0) {
+          const double mi = Minv[row * kLd + l];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) P[c] += mi * A[(k0 + c) * kLd + l];
+          l += 16;
+        }
+      }
+      double mv[3] = {0.0, 0.0, 0.0};   // Minv[row][k0 + c] for the block
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = k0 + c;
+        if (k >= n) break;
+        double acc = P[c];
+        if (l < k) {
+          const int b = l - k0;
+          acc += (b == 0 ? mv[0] : (b == 1 ? mv[1] : mv[2])) * A[k * kLd + l];
+        }
+        acc = row16_sum(acc);
+        const double val = (row < k) ? -acc * rv[k] : (row == k ? rv[k] : 0.0);
+        if (c < 3) mv[c] = val;
+        if (g == 0 && row <= k) Minv[row * kLd + k] = val;
       }
     }
     __syncthreads();
   }
-  return ok;
+  return !__syncthreads_or(!ok);
 }
 
 // LU factorization without pivoting of the leading n x n block of A = Q11 - S,
 // with S[k] = -sign(pivot) chosen at step k (so |U[k][k]| >= 1), plus U^{-1}
 // (Z) and L^{-1} (W, unit lower).  On exit A holds U's strict upper part and
 // the unscaled multipliers below the diagonal (L[i][k] = A[i][k] rcp[k]);
-// udiag[k] = U[k][k], rcp[k] = 1 / U[k][k], sgn[k] = S[k].  One barrier per
-// step; row k of W and column k of Z follow from the rows/columns before them.
+// udiag[k] = U[k][k], rcp[k] = 1 / U[k][k], sgn[k] = S[k].  Row r of Z and
+// column r of W follow from their own earlier entries:
+// Z[r][k] = -(sum_{l=r}^{k-1} Z[r][l] U[l][k]) / U[k][k],
+// W[k][r] = -sum_{l=r}^{k-1} L[k][l] W[l][r].
 RQ_DEV void lu_signed(double* A, double* Z, double* W, double* sgn, double* udiag, double* rcp,
-                      int n, int t) {
+                        int n, int t) {
+  const int lane = t & 63, wave = t >> 6;
   const int g = t & 15, row = t >> 4;
-  const int lane = t & 63, wave = t >> 6;     // wave w owns rows 4w..4w+3 of both parts
   for (int e = t; e < kPC * kLd; e += kPanelThreads) {
     Z[e] = 0.0;
     W[e] = 0.0;
   }
+  double a[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) a[q] = A[(4 * wave + q) * kLd + lane];
+  // the calling wave's rows k1..k1+3 among themselves, then stored
+  auto block_rows = [&](int k1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = k1 + c;
+      if (k >= n) break;
+      const double p = readlane_f64(a[c], k);
+      const double sk = (p >= 0.0) ? -1.0 : 1.0;
+      const double ukk = p - sk;
+      const double uinv = rcp_nr(ukk);
+      if (lane == 0) {
+        sgn[k] = sk;
+        udiag[k] = ukk;
+        rcp[k] = uinv;
+      }
+      const double ukj = uinv * a[c];
+#pragma unroll
+      for (int c2 = c + 1; c2 < 4; ++c2) {
+        const double m = readlane_f64(a[c2], k);                  // L multiplier A[k1 + c2][k]
+        if (k1 + c2 < n && lane > k && lane < n) a[c2] -= m * ukj;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k1 + q < n && lane < n) A[(k1 + q) * kLd + lane] = a[q];
+  };
+  if (wave == 0) block_rows(0);
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double p = A[k * kLd + k];
-    const double sk = (p >= 0.0) ? -1.0 : 1.0;
-    const double ukk = p - sk;
-    const double uinv = rcp_nr(ukk);
-    // trailing update A[i][j] -= L[i][k] U[k][j], lane = column j; waves whose
-    // rows are all <= k issue nothing
-    if (4 * wave + 3 > k) {
-      const double ukj = uinv * A[k * kLd + lane];
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    // the wave owning the next block is on the critical path: it goes first
+    const bool owner = wave == k0 / 4 + 1 && k0 + 4 < n;
+    if (owner) __builtin_amdgcn_s_setprio(3);
+    // rows below the block: A[i][j] -= A[i][k] (A[k][j] / U[k][k]), j > k, the
+    // multiplier A[i][k] read from the row itself after the block's earlier columns
+    if (4 * wave >= k0 + 4 && 4 * wave < n) {
+      double ak[4], rk[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = min(k0 + c, n - 1);
+        ak[c] = A[k * kLd + lane];
+        rk[c] = rcp[k];
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * wave + q;
-        if (i > k && i < n && lane > k && lane < n) A[i * kLd + lane] -= A[i * kLd + k] * ukj;
+        if (i >= n) break;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int k = k0 + c;
+          if (k >= n) break;
+          const double m = readlane_f64(a[q], k);
+          if (lane > k && lane < n) a[q] -= m * (rk[c] * ak[c]);
+        }
       }
     }
-    if (t == 0) {
-      sgn[k] = sk;
-      udiag[k] = ukk;
-      rcp[k] = uinv;
+    if (owner) {
+      block_rows(k0 + 4);
+      __builtin_amdgcn_s_setprio(0);
     }
-    // column k of U^{-1} (rows row < k) and row k of L^{-1} (columns row < k);
-    // rows beyond k issue nothing
-    if (4 * wave <= k) {
-      double az = 0.0, aw = 0.0;
-      for (int l = row + g; l < k; l += 16) {
-        az += Z[row * kLd + l] * A[l * kLd + k];
-        aw += A[k * kLd + l] * rcp[l] * W[l * kLd + row];
+    // column k of U^{-1} (rows < k) and row k of L^{-1} (columns < k), k = k0..k0+3,
+    // with the partial sums over l < k0 first as for R^{-1} above
+    if (row <= k0 + 3) {
+      double pz[4] = {0.0, 0.0, 0.0, 0.0}, pw[4] = {0.0, 0.0, 0.0, 0.0};
+      int l = row + g;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (l < k0) {
+          const double zi = Z[row * kLd + l];
+          const double wi = W[l * kLd + row];
+          const double rl = rcp[l];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            pz[c] += zi * A[l * kLd + k0 + c];
+            pw[c] += A[(k0 + c) * kLd + l] * rl * wi;
+          }
+          l += 16;
+        }
       }
-      az = row16_sum(az);
-      aw = row16_sum(aw);
-      if (g == 0) {
-        if (row < k) {
-          Z[row * kLd + k] = -az * uinv;
-          W[k * kLd + row] = -aw;
-        } else if (row == k) {
-          Z[k * kLd + k] = uinv;
-          W[k * kLd + k] = 1.0;
+      double zv[3] = {0.0, 0.0, 0.0}, wv[3] = {0.0, 0.0, 0.0};   // Z[row][k0 + c], W[k0 + c][row]
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = k0 + c;
+        if (k >= n) break;
+        double az = pz[c], aw = pw[c];
+        if (l < k) {
+          const int b = l - k0;
+          const double zl = b == 0 ? zv[0] : (b == 1 ? zv[1] : zv[2]);
+          const double wl = b == 0 ? wv[0] : (b == 1 ? wv[1] : wv[2]);
+          az += zl * A[l * kLd + k];
+          aw += A[k * kLd + l] * rcp[l] * wl;
+        }
+        az = row16_sum(az);
+        aw = row16_sum(aw);
+        const double zval = (row < k) ? -az * rcp[k] : (row == k ? rcp[k] : 0.0);
+        const double wval = (row < k) ? -aw : (row == k ? 1.0 : 0.0);
+        if (c < 3) {
+          zv[c] = zval;
+          wv[c] = wval;
+        }
+        if (g == 0 && row <= k) {
+          Z[row * kLd + k] = zval;
+          W[k * kLd + row] = wval;
         }
       }
     }
