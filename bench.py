@@ -545,6 +545,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=int, default=8)
+    ap.add_argument("--only", default="", choices=["", "trqrcp", "tuxv", "serving"],
+                    help="run only this secondary workload and print its result (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -562,10 +564,15 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    workloads = (("trqrcp_mixed_20000", bench_trqrcp_c3), ("tuxv_mixed_50000x8000", bench_tuxv_c4),
+                 ("serving", bench_serve_c5))
+    if args.only:
+        name, fn = next(w for w in workloads if w[0].split("_")[0] == args.only)
+        print(json.dumps({name: fn(args)}), flush=True)
+        return
     res = bench_rqrcp(args)
     secondary = {}
-    for name, fn in (("trqrcp_mixed_20000", bench_trqrcp_c3), ("tuxv_mixed_50000x8000", bench_tuxv_c4),
-                     ("serving", bench_serve_c5)):
+    for name, fn in workloads:
         if name.split("_")[0] in args.skip:
             continue
         try:
