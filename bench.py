@@ -14,7 +14,9 @@ its per-kernel times are the reported breakdown (`kernels_ms_per_step`, with the
 wall time of that step as `profiled_ms_per_step`) and its longest kernel class
 is the one the roofline covers.  The timed steps bracket only that class with
 events (two per launch), since events around every launch add device time of
-their own; the plain QRCP comparator is timed with no events at all.
+their own; the plain QRCP comparator and the repeated-sampling RQRCP
+(Section 3.2: a fresh sketch of each trailing matrix instead of the sample
+update) are timed with no events at all.
 
 Prints progress on stderr and one JSON line on stdout.
 """
@@ -266,6 +268,41 @@ def bench_rqrcp(args):
         log(f"plain QRCP {qms:.2f} ms/step -> RQRCP speedup {qms / ms:.2f}x")
         del qcopies
 
+    resampled = None
+    if not args.no_resample:
+        # RQRCP with repeated sampling (Section 3.2) on the same matrix: each block
+        # sketches its updated trailing matrix with a fresh Omega instead of the
+        # sample update (slice 0 is the Omega above, so block 0 is the same)
+        nblk = (n + b - 1) // b
+        oms = torch.empty((nblk, m, ell), dtype=torch.float64, device=dev)
+        oms[0] = torch.from_numpy(np.ascontiguousarray(om.T)).to(dev)
+        for j in range(1, nblk):
+            oms[j] = torch.from_numpy(np.ascontiguousarray(
+                synth.omega(ell, m, synth.seed_for(1, "Omega") + 100 + j).T)).to(dev)
+        rsteps = max(1, min(args.steps, 2))
+        rcopies = [A0.clone(memory_format=torch.preserve_format) for _ in range(rsteps + 2)]
+        log(f"repeated sampling: 1 warmup + 1 profiled + {rsteps} timed step(s)")
+        api.rsrqrcp_factor(rcopies[0], oms, b, p, handle=h)
+        h.sync()
+        rpms, rprof, _ = profiled_step(lambda: api.rsrqrcp_factor(rcopies[1], oms, b, p, handle=h), h)
+        lib.rq_profile_classes(h.ptr, 0)
+        torch.cuda.synchronize()
+        tr0 = time.perf_counter()
+        for i in range(rsteps):
+            api.rsrqrcp_factor(rcopies[2 + i], oms, b, p, handle=h)
+        torch.cuda.synchronize()
+        tr1 = time.perf_counter()
+        lib.rq_profile_classes(h.ptr, ALL_CLASSES)
+        h.sync()
+        rms = (tr1 - tr0) * 1e3 / rsteps
+        resampled = {"ms_per_step": round(rms, 3), "value": round(flops / (rms * 1e-3) / 1e12, 4),
+                     "unit": "TFLOP/s", "steps": rsteps,
+                     "sample_update_saving": round(1.0 - ms / rms, 4),
+                     "profiled_ms_per_step": round(rpms, 3),
+                     "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in rprof.items()}}
+        log(f"repeated sampling {rms:.2f} ms/step: the sample update saves {1.0 - ms / rms:.1%}")
+        del rcopies, oms
+
     roof = roofline(prof, args.steps, f"rqrcp_fp64_{m}x{n}_gauss")
     roof["share_of_step"] = round(prof[roof["kernel"]]["ms"] / args.steps / ms, 4)
     res = {
@@ -288,6 +325,7 @@ def bench_rqrcp(args):
         "profiled_ms_per_step": round(pms, 3),
         "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in breakdown.items()},
         "plain_qrcp": plain,
+        "repeated_sampling": resampled,
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
@@ -535,6 +573,8 @@ def main():
     ap.add_argument("--cpu-k", type=int, default=512, help="pivots of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-QRCP comparison")
+    ap.add_argument("--no-resample", action="store_true",
+                    help="skip the repeated-sampling RQRCP comparison")
     ap.add_argument("--skip", default="", help="comma list of secondary workloads to skip: "
                     "trqrcp,tuxv,serving")
     ap.add_argument("--c3-steps", type=int, default=3)

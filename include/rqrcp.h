@@ -120,6 +120,26 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
                        int64_t* jpvt, double* tau, double* T, int64_t ldt);
 
 /*
+ * rsrqrcp_factor -- RQRCP with repeated sampling (Section 3.2): Algorithm 4
+ * with the sample update replaced by a fresh sample of the trailing matrix,
+ * B^[J] = Omega^[J] A^[J], after each block's trailing update.  It is the
+ * baseline the sample update formula is measured against (one more pass over
+ * the trailing matrix per block) and the fallback when a sample update would
+ * lose accuracy.
+ *
+ * Same arguments, layout and results as rqrcp_factor, except:
+ *  Omegas, ldo  in: nblk = ceil(k / b) slices of ell x m, ldo >= ell; slice J
+ *            starts at Omegas + J * ostride, and block J (first column J b)
+ *            uses its first m - J b columns as Omega^[J].  Not modified.
+ *  ostride   distance between slices in doubles, ostride >= ldo * m.
+ * Argument numbers for errors: h=1 m=2 n=3 k=4 b=5 p=6 A=7 lda=8 Omegas=9
+ * ldo=10 ostride=11 jpvt=12 tau=13 T=14 ldt=15.
+ */
+rq_status rsrqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
+                         double* A, int64_t lda, const double* Omegas, int64_t ldo,
+                         int64_t ostride, int64_t* jpvt, double* tau, double* T, int64_t ldt);
+
+/*
  * qrcp_factor -- plain column-pivoted QR on the GPU, Algorithm 2 (QRCP with
  * BLAS-3 reflection blocking, Section 2.1): every pivot is the column of
  * largest trailing 2-norm of the full matrix, the column is brought up to date

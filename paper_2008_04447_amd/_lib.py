@@ -23,6 +23,8 @@ SIGNATURES = {
     "rq_last_error": (ctypes.c_char_p, [c_p]),
     "rqrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
                                       c_i64, c_p, c_p, c_p, c_i64]),
+    "rsrqrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
+                                        c_i64, c_i64, c_p, c_p, c_p, c_i64]),
     "qrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p, c_p]),
     "trqrcp_truncate": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_i64, c_i64,
                                          c_p, c_i64, c_p, c_i64, c_p, c_p, c_i64, c_p, c_i64,

@@ -120,6 +120,32 @@ def rqrcp_factor(A, Omega, b, p, k=None, handle=None):
     return jpvt, tau, T
 
 
+def rsrqrcp_factor(A, Omegas, b, p, k=None, handle=None):
+    """RQRCP with repeated sampling (Section 3.2) in place on A.
+
+    Omegas is a float64 device tensor of ceil(k / b) column-major ell x m
+    slices (shape (nblk, m, ell) with unit stride along ell, i.e. slice J is
+    Omegas[J].T); block J uses the first m - J b columns of slice J.
+    Returns (jpvt, tau, T) like rqrcp_factor."""
+    h = handle or default_handle(A.device.index)
+    m, n = A.shape
+    k = min(m, n) if k is None else int(k)
+    ell = b + p
+    nblk = (k + b - 1) // b
+    if Omegas.dim() != 3 or Omegas.shape[0] < nblk or Omegas.shape[1] != m or \
+            Omegas.shape[2] != ell or Omegas.stride(2) != 1 or Omegas.stride(1) < ell:
+        raise ValueError("Omegas must be (nblk, m, ell) with unit stride along ell")
+    dev = A.device
+    jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
+    tau = torch.empty(max(k, 1), dtype=torch.float64, device=dev)[:k]
+    T = empty_colmajor(b, max(k, 1), torch.float64, dev)
+    rc = _lib.load().rsrqrcp_factor(h.ptr, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omegas),
+                                    Omegas.stride(1), Omegas.stride(0), _ptr(jpvt), _ptr(tau),
+                                    _ptr(T), ld(T))
+    _check("rsrqrcp_factor", rc, h)
+    return jpvt, tau, T
+
+
 def qrcp_factor(A, k=None, nb=32, handle=None):
     """Plain QRCP (Algorithm 2) in place on A; returns (jpvt, tau)."""
     h = handle or default_handle(A.device.index)

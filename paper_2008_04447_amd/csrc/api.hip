@@ -441,9 +441,16 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
   return run_sample_qrcp(h, B, ldb, (int)ell, n, (int)steps, w, perm);
 }
 
-rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
-                       double* A, int64_t lda, const double* Omega, int64_t ldo, int64_t* jpvt,
-                       double* tau, double* T, int64_t ldt) {
+}  // extern "C"
+
+// The block loop of Algorithm 4.  With `resample` (repeated sampling, Section
+// 3.2) the sample of block J is a fresh sketch of the updated trailing matrix,
+// B = Omega^[J] A^[J], with Omega^[J] the first m - Jb columns of the ell x m
+// slice Omega + J ostride, instead of the sample update (eq. update1).
+static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
+                            double* A, int64_t lda, const double* Omega, int64_t ldo,
+                            int64_t ostride, bool resample, int64_t* jpvt, double* tau, double* T,
+                            int64_t ldt) {
   if (!h) return -1;
   if (m < 0) return -2;
   if (n < 0 || n > RQ_MAX_N) return -3;
@@ -454,7 +461,8 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   if (lda < std::max<int64_t>(1, m)) return -8;
   const int64_t ell = b + p;
   if (k > 0 && ell > m) return -6;
-  if (!valid_ptr(Omega, k > 0 ? ell * m : 0)) return -9;
+  const int64_t nblk = (k + b - 1) / b;
+  if (!valid_ptr(Omega, k > 0 ? (resample ? ostride * (nblk - 1) + ldo * m : ell * m) : 0)) return -9;
   if (ldo < ell) return -10;
   if (!valid_ptr(jpvt, n)) return -11;
   if (!valid_ptr(tau, k)) return -12;
@@ -475,6 +483,8 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
     int ks_b, kc_b;
     plan_split((int)(m - c0), (int)nt, &ks_b, &kc_b);
     w_part = std::max(w_part, (size_t)ks_b * 64 * nt);
+    const int64_t c1 = c0 + std::min<int64_t>(b, k - c0);     // next block's sketch
+    if (resample && c1 < k) w_part = std::max(w_part, sketch_part_doubles((int)ell, m - c1, n - c1));
   }
   const size_t n_sample = (size_t)ell * n;
   const size_t n_part = std::max(w_part, sketch_part_doubles((int)ell, m, n));
@@ -597,6 +607,20 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
       RQ_CHECK(h, launch_reduce_r12(part, g.split_stride, ks, (int)Nt, zbuf, tj, ldtj, ybuf, m,
                                     Ctr, lda, bj, s));
     }
+    if (resample) {
+      // 5. A_trailing -= Y Z for the rows below R12, then 6'. the next sample,
+      // Omega^[J+1] times the updated trailing matrix
+      if (M > bj) {
+        const double Mr = (double)(M - bj), Nr = (double)Nt;
+        KTimer kt(h, K_UPDATE, 2.0 * bj * Mr * Nr, 8.0 * (2.0 * Mr * Nr + Mr * bj + (double)bj * Nr));
+        RQ_CHECK(h, launch_update(Ctr + bj, lda, (int)(M - bj), (int)Nt, ybuf + bj, m, zbuf, 64, bj,
+                                  h->update_wgs, s));
+      }
+      if (col0 + bj < k)
+        RQ_TRY(sketch_fp64(h, (int)ell, M - bj, Nt, Omega + (col0 / b + 1) * ostride, ldo,
+                           Ctr + bj, lda, sample + (col0 + bj) * ell, ell, part));
+      continue;
+    }
     // 5. A_trailing -= Y Z for the rows below R12: on the side stream alongside
     // the next sample QRCP (see release_side); the next block waits for them
     // before it permutes and factors its panel.
@@ -615,6 +639,23 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
   }
   if (pending_rows) RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
   return RQ_OK;
+}
+
+extern "C" {
+
+rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
+                       double* A, int64_t lda, const double* Omega, int64_t ldo, int64_t* jpvt,
+                       double* tau, double* T, int64_t ldt) {
+  return rqrcp_core(h, m, n, k, b, p, A, lda, Omega, ldo, 0, false, jpvt, tau, T, ldt);
+}
+
+rq_status rsrqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
+                         double* A, int64_t lda, const double* Omegas, int64_t ldo,
+                         int64_t ostride, int64_t* jpvt, double* tau, double* T, int64_t ldt) {
+  if (h && k > 0 && b >= 1 && ldo >= b + p && m > 0 && ostride < ldo * m) return -11;
+  rq_status r = rqrcp_core(h, m, n, k, b, p, A, lda, Omegas, ldo, ostride, true, jpvt, tau, T, ldt);
+  if (r <= -11 && r >= -14) r -= 1;   // jpvt, tau, T, ldt come after ostride here
+  return r;
 }
 
 }  // extern "C"

@@ -89,3 +89,16 @@ def test_sketch_and_sample_qrcp_validation(lib):
     assert lib.rq_sketch(FAKE, 0, 4, 10, 5, buf, 4, buf, 9, buf, 4) == -9
     assert lib.rq_sample_qrcp(FAKE, 8, 10, 9, buf, 8, buf) == -4
     assert lib.rq_sample_qrcp(FAKE, 8, 10, 4, buf, 7, buf) == -6
+
+
+def test_rsrqrcp_argument_numbering(lib):
+    """ostride is argument 11, so jpvt, tau, T, ldt report 12..15."""
+    buf = ctypes.c_void_p(0x2000)
+    args = (FAKE, 10, 6, 6, 2, 2, buf, 10)
+    assert lib.rsrqrcp_factor(None, 10, 6, 6, 2, 2, buf, 10, buf, 4, 40, buf, buf, None, 0) == -1
+    assert lib.rsrqrcp_factor(*args, None, 4, 40, buf, buf, None, 0) == -9
+    assert lib.rsrqrcp_factor(*args, buf, 3, 40, buf, buf, None, 0) == -10
+    assert lib.rsrqrcp_factor(*args, buf, 4, 39, buf, buf, None, 0) == -11
+    assert lib.rsrqrcp_factor(*args, buf, 4, 40, None, buf, None, 0) == -12
+    assert lib.rsrqrcp_factor(*args, buf, 4, 40, buf, None, None, 0) == -13
+    assert lib.rsrqrcp_factor(*args, buf, 4, 40, buf, buf, buf, 1) == -15
