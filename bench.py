@@ -416,6 +416,10 @@ def bench_trqrcp_c3(args):
         qk[:k, :] += torch.eye(k, dtype=torch.float64, device=dev)
         return float(torch.linalg.norm(ap - qk @ R) / torch.linalg.norm(A64))
     e32, e64 = err(out), err(out64)
+    # a second alternation (jmax = 2: the LQ of U^T A after the QR of A V)
+    ms2, out2, _, _ = _timed(lambda: api.tuxv_svd(A32, om, b, p, k, handle=h, jmax=2), 1, 1, h)
+    e2 = err(out2)
+    del out2
     opt = float(np.sqrt(np.sum(sig[k:] ** 2) / np.sum(sig ** 2)))
     fl = trqrcp_flops(m, n, k, b, p)
     roof = roofline(prof, args.c3_steps)
@@ -459,6 +463,10 @@ def bench_tuxv_c4(args):
         U, X, V, _ = o
         return float(torch.linalg.norm(A64 - U @ (X @ V.T)) / torch.linalg.norm(A64))
     e32, e64 = err(out), err(out64)
+    # a second alternation (jmax = 2: the LQ of U^T A after the QR of A V)
+    ms2, out2, _, _ = _timed(lambda: api.tuxv_svd(A32, om, b, p, k, handle=h, jmax=2), 1, 1, h)
+    e2 = err(out2)
+    del out2
     s32 = torch.linalg.svdvals(out[1]).cpu().numpy()
     s64 = torch.linalg.svdvals(out64[1]).cpu().numpy()
     rel = np.abs(s32 - s64) / s64
@@ -469,6 +477,7 @@ def bench_tuxv_c4(args):
            "approx_error": e32, "approx_error_fp64": e64, "error_ratio": round(e32 / e64, 5),
            "sigma_rel_err_median": float(np.median(rel)), "sigma_rel_err_max": float(rel.max()),
            "sigma_rel_err_median_top64": float(np.median(rel[:64])),
+           "jmax2": {"ms_per_step": round(ms2, 3), "approx_error": e2},
            "flops_per_step": fl, "roofline": roof,
            "kernels_ms_per_step": {kk: round(v["ms"], 3) for kk, v in brk.items()},
            "config": {"workload": "tuxv_mixed_50000x8000_poly1.5_noise1e-6", "m": m, "n": n, "k": k,

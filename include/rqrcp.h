@@ -204,6 +204,21 @@ rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, i
                    int64_t* jpvt);
 
 /*
+ * tuxv_svd_iter -- TUXV with jmax >= 1 alternations (Algorithm 6, Section
+ * 4.2).  Step 1 is tuxv_svd; each further step alternates the LQ of
+ * Z = U^T A (a new V, X = R^T lower triangular) and the QR of Z = A V (a new U,
+ * X upper triangular), so A ~ U X V^T with X upper for odd jmax and lower for
+ * even jmax.  Every step is one more pass over A (two for U^T A when k > 64:
+ * its rows are formed in chunks of 64); in mixed precision the products with
+ * A use BF16 operands and FP32 accumulation like the first step.
+ * Same arguments and results as tuxv_svd, plus jmax (argument 19, >= 1).
+ */
+rq_status tuxv_svd_iter(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
+                        int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
+                        double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
+                        int64_t* jpvt, int64_t jmax);
+
+/*
  * rq_sketch -- the sketch B = Omega A alone (the first step of Algorithms 3-5).
  *  prec      RQ_FP64 (A double) or RQ_MIXED_BF16 (A float, BF16 MFMA).
  *  ell, m, n sizes: Omega is ell x m, A is m x n, B is ell x n (double).

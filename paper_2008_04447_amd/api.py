@@ -178,8 +178,9 @@ def trqrcp_truncate(A, Omega, b, p, k, handle=None):
     return jpvt, Y, T, R
 
 
-def tuxv_svd(A, Omega, b, p, k, handle=None):
-    """TUXV (Algorithm 6, j_max = 1).  Returns (U, X, V, jpvt) with A ~ U X V^T."""
+def tuxv_svd(A, Omega, b, p, k, handle=None, jmax=1):
+    """TUXV (Algorithm 6, jmax alternations).  Returns (U, X, V, jpvt) with
+    A ~ U X V^T (X upper for odd jmax, lower for even)."""
     h = handle or default_handle(A.device.index)
     m, n = A.shape
     dev = A.device
@@ -188,8 +189,14 @@ def tuxv_svd(A, Omega, b, p, k, handle=None):
     X = empty_colmajor(k, k, torch.float64, dev)
     V = empty_colmajor(n, k, torch.float64, dev)
     jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
-    rc = _lib.load().tuxv_svd(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega), ld(Omega),
-                              _ptr(U), ld(U), _ptr(X), ld(X), _ptr(V), ld(V), _ptr(jpvt))
+    if jmax == 1:
+        rc = _lib.load().tuxv_svd(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
+                                  ld(Omega), _ptr(U), ld(U), _ptr(X), ld(X), _ptr(V), ld(V),
+                                  _ptr(jpvt))
+    else:
+        rc = _lib.load().tuxv_svd_iter(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
+                                       ld(Omega), _ptr(U), ld(U), _ptr(X), ld(X), _ptr(V), ld(V),
+                                       _ptr(jpvt), int(jmax))
     _check("tuxv_svd", rc, h)
     return U, X, V, jpvt
 

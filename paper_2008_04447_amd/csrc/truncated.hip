@@ -326,13 +326,14 @@ static rq_status form_q(rq_handle h, const double* A, int64_t lda, int64_t M, in
   return RQ_OK;
 }
 
-// TUXV state beside the TRQRCP work: Y, T, R, Z0^T, Z1, two T stacks, tau and
-// the BF16 staging of V (carved in this order by tuxv_svd).
+// TUXV state beside the TRQRCP work: Y, T, R, Z0^T, Z1, two T stacks, tau, the
+// BF16 staging of V and an identity column map (carved in this order by tuxv_core).
 static size_t tuxv_extra_bytes(int64_t m, int64_t n, int64_t k) {
   return padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) + padded_bytes((size_t)k * n) +
          padded_bytes((size_t)n * k) + padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
          padded_bytes((size_t)k + 64) +
-         padded_bytes((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4);
+         padded_bytes((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4) +
+         padded_bytes((size_t)std::max(n, k));
 }
 
 size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv) {
@@ -389,10 +390,13 @@ extern "C" rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64
                      T, ldt, R, ldr, w);
 }
 
-extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
-                              int64_t b, int64_t p, const void* A, int64_t lda,
-                              const double* Omega, int64_t ldo, double* U, int64_t ldu, double* X,
-                              int64_t ldx, double* V, int64_t ldv, int64_t* jpvt) {
+// Algorithm 6 with jmax alternations: after Z1 = A V1 and its QR, each further
+// step forms Z = U^T A and the LQ of Z (QR of Z^T) for a new V and a lower X,
+// then Z = A V and its QR for a new U and an upper X, until jmax steps.
+static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
+                           int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
+                           double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
+                           int64_t* jpvt, int64_t jmax) {
   RQ_TRY(check_common(h, prec, m, n, k, b, p, A, lda, Omega, ldo));
   if (!valid_ptr(U, m * k)) return -12;
   if (ldu < std::max<int64_t>(1, m)) return -13;
@@ -422,6 +426,7 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   double* tauq = cv.take<double>((size_t)k + 64);
   __bf16* vbf = reinterpret_cast<__bf16*>(
       cv.take<double>((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4));   // V as BF16
+  int64_t* ident = cv.take<int64_t>((size_t)std::max(n, k));                          // 0, 1, 2, ...
   const bool f32 = prec == RQ_MIXED_BF16;
   hipStream_t s = h->stream;
   // 1. TRQRCP: A P ~ Q R
@@ -434,24 +439,85 @@ extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, i
   // 3. LQ of Z0 = QR of Z0^T: V = Q[:, 0:k]
   RQ_TRY(qr_blocked(h, Z0T, n, n, k, tauq, Tb, w));
   RQ_TRY(form_q(h, Z0T, n, n, k, Tb, V, ldv, w));
-  // 4. Z1 = A V (the one extra pass over A)
-  {
-    // algorithmic bytes: A once (FP32 or FP64), V and Z1 in FP64
-    KTimer kt(h, f32 ? K_INNER_BF16 : K_INNER, 2.0 * (double)m * n * k,
-              (f32 ? 4.0 : 8.0) * (double)m * n + 8.0 * ((double)n * k + (double)m * k));
-    if (f32)
-      RQ_CHECK(h, launch_gemm_nn_bf16(Z1, m, (int)m, (int)k, static_cast<const float*>(A), lda, V,
-                                      ldv, (int)n, vbf, s));
-    else
-      RQ_CHECK(h, launch_gemm_nn(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda, V, ldv,
-                                 (int)n, 1.0, 0.0, s));
+  for (int64_t j = 1;; j += 2) {
+    // 4. Z1 = A V (the one extra pass over A)
+    {
+      // algorithmic bytes: A once (FP32 or FP64), V and Z1 in FP64
+      KTimer kt(h, f32 ? K_INNER_BF16 : K_INNER, 2.0 * (double)m * n * k,
+                (f32 ? 4.0 : 8.0) * (double)m * n + 8.0 * ((double)n * k + (double)m * k));
+      if (f32)
+        RQ_CHECK(h, launch_gemm_nn_bf16(Z1, m, (int)m, (int)k, static_cast<const float*>(A), lda, V,
+                                        ldv, (int)n, vbf, s));
+      else
+        RQ_CHECK(h, launch_gemm_nn(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda, V, ldv,
+                                   (int)n, 1.0, 0.0, s));
+    }
+    // 5. QR of Z1: U = Q[:, 0:k], X = upper factor
+    RQ_TRY(qr_blocked(h, Z1, m, m, k, tauq, Tb2, w));
+    {
+      KTimer kt(h, K_OTHER, 0.0, 16.0 * (double)k * k);
+      RQ_CHECK(h, launch_copy_upper(Z1, m, (int)k, (int)k, X, ldx, s));
+    }
+    RQ_TRY(form_q(h, Z1, m, m, k, Tb2, U, ldu, w));
+    if (j == jmax) break;
+    // 6. Z = U^T A (k x n, rows of U^T in chunks of 64 into R's place), its
+    // transpose into Z0T, and the LQ of Z: V = Q of Z^T, X = R^T (lower)
+    if (j == 1) RQ_CHECK(h, launch_iota(ident, (int)std::max(n, k), s));
+    for (int64_t c0 = 0; c0 < k; c0 += 64) {
+      const int pc = (int)std::min<int64_t>(64, k - c0);
+      if (f32) {
+        GemmArgsF g{};
+        g.L = U + c0 * ldu;
+        g.sLp = ldu;
+        g.sLk = 1;
+        g.X = static_cast<const float*>(A);
+        g.ldx = lda;
+        g.P = pc;
+        g.K = (int)m;
+        g.N = (int)n;
+        RQ_TRY(gemm_lx_bf16_reduced(h, K_INNER_BF16, g, w.part, Rw + c0, k, w.lbf));
+      } else {
+        GemmArgs g{};
+        g.L = U + c0 * ldu;
+        g.sLp = ldu;
+        g.sLk = 1;
+        g.X = static_cast<const double*>(A);
+        g.ldx = lda;
+        g.P = pc;
+        g.K = (int)m;
+        g.N = (int)n;
+        RQ_TRY(gemm_lx_reduced(h, K_INNER, g, w.part, Rw + c0, k));
+      }
+    }
+    {
+      KTimer kt(h, K_OTHER, 0.0, 16.0 * (double)k * n);
+      RQ_CHECK(h, launch_scatter_t(Rw, k, (int)k, (int)n, ident, Z0T, n, s));
+    }
+    RQ_TRY(qr_blocked(h, Z0T, n, n, k, tauq, Tb, w));
+    {
+      KTimer kt(h, K_OTHER, 0.0, 32.0 * (double)k * k);
+      RQ_CHECK(h, launch_copy_upper(Z0T, n, (int)k, (int)k, Tw, k, s));
+      RQ_CHECK(h, launch_scatter_t(Tw, k, (int)k, (int)k, ident, X, ldx, s));
+    }
+    RQ_TRY(form_q(h, Z0T, n, n, k, Tb, V, ldv, w));
+    if (j + 1 == jmax) break;
   }
-  // 5. QR of Z1: U = Q[:, 0:k], X = upper factor
-  RQ_TRY(qr_blocked(h, Z1, m, m, k, tauq, Tb2, w));
-  {
-    KTimer kt(h, K_OTHER, 0.0, 16.0 * (double)k * k);
-    RQ_CHECK(h, launch_copy_upper(Z1, m, (int)k, (int)k, X, ldx, s));
-  }
-  RQ_TRY(form_q(h, Z1, m, m, k, Tb2, U, ldu, w));
   return RQ_OK;
+}
+
+extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
+                              int64_t b, int64_t p, const void* A, int64_t lda,
+                              const double* Omega, int64_t ldo, double* U, int64_t ldu, double* X,
+                              int64_t ldx, double* V, int64_t ldv, int64_t* jpvt) {
+  return tuxv_core(h, prec, m, n, k, b, p, A, lda, Omega, ldo, U, ldu, X, ldx, V, ldv, jpvt, 1);
+}
+
+extern "C" rq_status tuxv_svd_iter(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
+                                   int64_t b, int64_t p, const void* A, int64_t lda,
+                                   const double* Omega, int64_t ldo, double* U, int64_t ldu,
+                                   double* X, int64_t ldx, double* V, int64_t ldv, int64_t* jpvt,
+                                   int64_t jmax) {
+  if (!h) return -1;
+  if (jmax < 1) return -19;
+  return tuxv_core(h, prec, m, n, k, b, p, A, lda, Omega, ldo, U, ldu, X, ldx, V, ldv, jpvt, jmax);
 }

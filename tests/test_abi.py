@@ -102,3 +102,10 @@ def test_rsrqrcp_argument_numbering(lib):
     assert lib.rsrqrcp_factor(*args, buf, 4, 40, None, buf, None, 0) == -12
     assert lib.rsrqrcp_factor(*args, buf, 4, 40, buf, None, None, 0) == -13
     assert lib.rsrqrcp_factor(*args, buf, 4, 40, buf, buf, buf, 1) == -15
+
+
+def test_tuxv_iter_jmax_is_argument_19(lib):
+    buf = ctypes.c_void_p(0x2000)
+    args = (0, 10, 8, 4, 2, 2, buf, 10, buf, 4, buf, 10, buf, 4, buf, 8, buf)
+    assert lib.tuxv_svd_iter(None, *args, 1) == -1
+    assert lib.tuxv_svd_iter(FAKE, *args, 0) == -19

@@ -103,3 +103,56 @@ def test_tuxv_exact_rank_recovers_spectrum(api):
     api.default_handle(0).sync()
     s = np.linalg.svd(X.cpu().numpy(), compute_uv=False)
     np.testing.assert_allclose(s, sig, rtol=1e-11)
+
+
+@pytest.mark.parametrize("m,n,k,b,p,jmax", [
+    (300, 200, 40, 16, 8, 2),     # k <= 64: U^T A in one chunk
+    (300, 200, 40, 16, 8, 3),
+    (400, 350, 100, 32, 8, 2),    # k > 64: U^T A in two chunks of rows
+    (400, 350, 100, 32, 8, 3),
+])
+def test_tuxv_iterations_match_oracle(api, m, n, k, b, p, jmax):
+    """Algorithm 6 with jmax alternations: closed forms, triangularity and the
+    oracle's singular values and error."""
+    a = _case(m, n, 6300 + m + jmax, min(m, n) / 5.0)
+    om = synth.omega(b + p, m, 6302 + n)
+    U, X, V, jpvt = api.tuxv_svd(_dev(api, a), _dev(api, om), b, p, k, jmax=jmax)
+    api.default_handle(0).sync()
+    U, X, V, jpvt = (x.cpu().numpy() for x in (U, X, V, jpvt))
+    ref = oracle.tuxv(a, om, b, p, k, jmax=jmax)
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-13)
+    np.testing.assert_allclose(V.T @ V, np.eye(k), atol=1e-13)
+    tri = np.triu(X) if jmax % 2 else np.tril(X)
+    np.testing.assert_array_equal(X, tri)
+    approx = U @ X @ V.T
+    closed = a @ V @ V.T if jmax % 2 else U @ (U.T @ a)   # the last step's projection
+    np.testing.assert_allclose(approx, closed, atol=1e-12 * np.abs(a).max())
+    sig = np.linalg.svd(X, compute_uv=False)
+    e_gpu = np.linalg.norm(a - approx)
+    e_ref = np.linalg.norm(a - ref.u @ ref.x @ ref.v.T)
+    pre = ref.trq.trace.prefix(ref.trq.sample_scale, REL, ABS)
+    if pre >= k:
+        np.testing.assert_allclose(sig, ref.sigma, rtol=1e-9, atol=1e-13 * sig[0])
+        assert abs(e_gpu - e_ref) <= 1e-9 * e_ref + 1e-13 * np.linalg.norm(a)
+    sv = np.linalg.svd(a, compute_uv=False)
+    assert np.all(sig <= sv[:k] * (1 + 1e-10))
+    assert e_gpu >= np.sqrt(np.sum(sv[k:] ** 2)) * (1 - 1e-10)
+
+
+def test_tuxv_iterations_mixed_error_ratio(api):
+    m, n, k, b, p, jmax = 1500, 600, 96, 32, 8, 2
+    sig = synth.spectrum("poly", min(m, n), power=1.5)
+    a64 = synth.low_rank(m, n, sig, 6400, 6401) + 1e-6 * synth.gaussian((m, n), 6402)
+    a32 = a64.astype(np.float32)
+    a = a32.astype(np.float64)
+    om = synth.omega(b + p, m, 6403)
+    A = api.colmajor(a32, dtype=torch.float32, device=torch.device("cuda", 0))
+    U, X, V, _ = api.tuxv_svd(A, _dev(api, om), b, p, k, jmax=jmax)
+    api.default_handle(0).sync()
+    U, X, V = (x.cpu().numpy() for x in (U, X, V))
+    ref = oracle.tuxv(a, om, b, p, k, jmax=jmax)
+    e_mix = np.linalg.norm(a - U @ X @ V.T) / np.linalg.norm(a)
+    e_ref = np.linalg.norm(a - ref.u @ ref.x @ ref.v.T) / np.linalg.norm(a)
+    print(f"TUXV jmax={jmax} error mixed {e_mix:.6e} vs FP64 {e_ref:.6e}")
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-12)
+    assert e_mix <= 1.05 * e_ref
