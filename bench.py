@@ -416,10 +416,6 @@ def bench_trqrcp_c3(args):
         qk[:k, :] += torch.eye(k, dtype=torch.float64, device=dev)
         return float(torch.linalg.norm(ap - qk @ R) / torch.linalg.norm(A64))
     e32, e64 = err(out), err(out64)
-    # a second alternation (jmax = 2: the LQ of U^T A after the QR of A V)
-    ms2, out2, _, _ = _timed(lambda: api.tuxv_svd(A32, om, b, p, k, handle=h, jmax=2), 1, 1, h)
-    e2 = err(out2)
-    del out2
     opt = float(np.sqrt(np.sum(sig[k:] ** 2) / np.sum(sig ** 2)))
     fl = trqrcp_flops(m, n, k, b, p)
     roof = roofline(prof, args.c3_steps)

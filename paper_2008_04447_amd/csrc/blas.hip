@@ -1019,22 +1019,17 @@ __global__ void tcomp1_kernel(const double* G, const double* T2, int64_t ldt2, i
   for (int q = 0; q <= c; ++q) acc += G[q + (int64_t)i * 64] * T2[q + (int64_t)c * ldt2];
   X1[i + (int64_t)c * c0] = acc;
 }
-// T(i, c0 + c) = -sum_{s = i}^{c0-1} T(i, s) X1(s, c)
-__global__ void tcomp2_kernel(double* T, int64_t ldt, int c0, int bj, const double* X1) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int c = blockIdx.y;
-  if (i >= c0 || c >= bj) return;
-  double acc = 0.0;
-  for (int s2 = i; s2 < c0; ++s2) acc += T[i + (int64_t)s2 * ldt] * X1[s2 + (int64_t)c * c0];
-  T[i + (int64_t)(c0 + c) * ldt] = -acc;
-}
+// T12 = -T11 X1 with X1 = G^T T2 (c0 x bj): T11 is upper triangular with exact
+// zeros below the diagonal, so the product runs as a plain matrix product on
+// the matrix cores, straight into T(0:c0, c0:c0+bj).
 hipError_t launch_tcompose(double* T, int64_t ldt, int c0, int bj, const double* G,
                            const double* T2, int64_t ldt2, double* X1, hipStream_t s) {
   if (c0 <= 0 || bj <= 0) return hipSuccess;
   dim3 grid((c0 + 255) / 256, bj);
   hipLaunchKernelGGL(tcomp1_kernel, grid, dim3(256), 0, s, G, T2, ldt2, c0, bj, X1);
-  hipLaunchKernelGGL(tcomp2_kernel, grid, dim3(256), 0, s, T, ldt, c0, bj, X1);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gemm_nn(T + (int64_t)c0 * ldt, ldt, c0, bj, T, ldt, X1, c0, c0, -1.0, 0.0, s);
 }
 
 __global__ void scatter_t_kernel(const double* R, int64_t ldr, int k, int n, const int64_t* col,
