@@ -647,6 +647,133 @@ __global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int
     }
 }
 
+// ---- C(M x N) = Y(M x K) Z(K x N) for tall Y and N <= 256 (Z1 = A V of TUXV) --
+// One pass over Y: a workgroup owns 64 rows of C and 64 NBW columns (all of N
+// when N <= 256).  Z is staged once, step-major: element (k, c) at
+// ((k / 4) ncp + c) 4 + k % 4, so a wave's Z operands of one 4-k step are 64
+// consecutive doubles; Y operands come straight from Y (16 consecutive rows per
+// 4 lanes).  Wave w owns columns 16 NBW w ..; the operands of the next two steps
+// are in flight (a ring of three register sets).  Rows at or past M are clamped
+// to row M - 1 and not stored; Z is zero past K and N.
+constexpr int kNf64Rows = 64;
+
+static int nf64_nbw(int N) { return N > 192 ? 4 : N > 128 ? 3 : N > 64 ? 2 : 1; }
+static int nf64_ncp(int N) {
+  const int cols = 64 * nf64_nbw(N);
+  return ((N + cols - 1) / cols) * cols;
+}
+int64_t gemm_nn_tall_stage_doubles(int N, int K) {
+  return (int64_t)nf64_ncp(N) * (((K + 3) / 4) * 4);
+}
+
+__global__ void stage_z_f64_kernel(const double* Z, int64_t ldz, int N, int K, int ncp, int64_t total,
+                                   double* zt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int kk = (int)(e & 3);
+  const int64_t sc = e >> 2;
+  const int c = (int)(sc % ncp);
+  const int k = (int)(sc / ncp) * 4 + kk;
+  zt[e] = (c < N && k < K) ? Z[k + (int64_t)c * ldz] : 0.0;
+}
+
+template <int NBW>
+__global__ __launch_bounds__(256, 2) void gemm_nn_tall_kernel(double* C, int64_t ldc, int M, int N,
+                                                              const double* Y, int64_t ldy,
+                                                              const double* zt, int ncp, int K,
+                                                              double alpha) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int r0 = blockIdx.x * kNf64Rows;
+  const int cw = blockIdx.y * 64 * NBW + 16 * NBW * wave;
+  const double* yp[4];
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib) yp[ib] = Y + min(r0 + 16 * ib + l16, M - 1) + (int64_t)kq * ldy;
+  const double* zp = zt + (int64_t)(cw + l16) * 4 + kq;
+  dx4 acc[4][NBW];
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = dx4{0.0, 0.0, 0.0, 0.0};
+  struct Ops {
+    double y[4], z[NBW];
+  };
+  auto load = [&](int st, Ops& o) {
+    const int64_t yo = (int64_t)(4 * st) * ldy;
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) o.y[ib] = yp[ib][yo];
+#pragma unroll
+    for (int jb = 0; jb < NBW; ++jb) o.z[jb] = zp[((int64_t)st * ncp + 16 * jb) * 4];
+  };
+  auto compute = [&](const Ops& o) {
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = mfma_f64(o.y[ib], o.z[jb], acc[ib][jb]);
+  };
+  const int nfull = K / 4;
+  {
+    Ops A, B, Cr;
+    if (nfull > 0) load(0, A);
+    if (nfull > 1) load(1, B);
+    for (int i = 0; i < nfull; i += 3) {
+      if (i + 2 < nfull) load(i + 2, Cr);
+      compute(A);
+      if (i + 1 >= nfull) break;
+      if (i + 3 < nfull) load(i + 3, A);
+      compute(B);
+      if (i + 2 >= nfull) break;
+      if (i + 4 < nfull) load(i + 4, B);
+      compute(Cr);
+    }
+  }
+  if (4 * nfull < K) {                            // a final partial step
+    Ops o;
+    const bool kok = 4 * nfull + kq < K;
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) o.y[ib] = kok ? yp[ib][(int64_t)(4 * nfull) * ldy] : 0.0;
+#pragma unroll
+    for (int jb = 0; jb < NBW; ++jb) o.z[jb] = zp[((int64_t)nfull * ncp + 16 * jb) * 4];
+    compute(o);
+  }
+  // lane holds C(r0 + 16 ib + kq + 4 v, cw + 16 jb + l16)
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < NBW; ++jb) {
+      const int c = cw + 16 * jb + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * ib + kq + 4 * v;
+        if (r < M && c < N) C[r + (int64_t)c * ldc] = alpha * acc[ib][jb][v];
+      }
+    }
+}
+
+hipError_t launch_gemm_nn_tall(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
+                               const double* Z, int64_t ldz, int K, double alpha, double* zstage,
+                               hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (ldy < M || ldc < M || (K > 0 && !zstage)) return hipErrorInvalidValue;
+  const int nbw = nf64_nbw(N), ncp = nf64_ncp(N);
+  const int64_t total = gemm_nn_tall_stage_doubles(N, K);
+  if (total > 0) {
+    hipLaunchKernelGGL(stage_z_f64_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       Z, ldz, N, K, ncp, total, zstage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((M + kNf64Rows - 1) / kNf64Rows, ncp / (64 * nbw));
+  switch (nbw) {
+    case 1: hipLaunchKernelGGL(gemm_nn_tall_kernel<1>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
+    case 2: hipLaunchKernelGGL(gemm_nn_tall_kernel<2>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
+    case 3: hipLaunchKernelGGL(gemm_nn_tall_kernel<3>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
+    default: hipLaunchKernelGGL(gemm_nn_tall_kernel<4>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_nn(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
                           const double* Z, int64_t ldz, int K, double alpha, double beta,
                           hipStream_t s) {

@@ -326,14 +326,19 @@ static rq_status form_q(rq_handle h, const double* A, int64_t lda, int64_t M, in
   return RQ_OK;
 }
 
+// V staged for the product Z1 = A V: BF16 (mixed) or FP64, one buffer for both.
+static size_t vstage_doubles(int64_t n, int64_t k) {
+  return std::max((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4,
+                  (size_t)gemm_nn_tall_stage_doubles((int)k, (int)n));
+}
+
 // TUXV state beside the TRQRCP work: Y, T, R, Z0^T, Z1, two T stacks, tau, the
-// BF16 staging of V and an identity column map (carved in this order by tuxv_core).
+// staging of V and an identity column map (carved in this order by tuxv_core).
 static size_t tuxv_extra_bytes(int64_t m, int64_t n, int64_t k) {
   return padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) + padded_bytes((size_t)k * n) +
          padded_bytes((size_t)n * k) + padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
          padded_bytes((size_t)k + 64) +
-         padded_bytes((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4) +
-         padded_bytes((size_t)std::max(n, k));
+         padded_bytes(vstage_doubles(n, k)) + padded_bytes((size_t)std::max(n, k));
 }
 
 size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv) {
@@ -424,8 +429,7 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
   double* Tb = cv.take<double>((size_t)64 * k);
   double* Tb2 = cv.take<double>((size_t)64 * k);
   double* tauq = cv.take<double>((size_t)k + 64);
-  __bf16* vbf = reinterpret_cast<__bf16*>(
-      cv.take<double>((size_t)(gemm_nn_bf16_stage_elems((int)k, (int)n) + 3) / 4));   // V as BF16
+  double* vstage = cv.take<double>(vstage_doubles(n, k));                             // V staged
   int64_t* ident = cv.take<int64_t>((size_t)std::max(n, k));                          // 0, 1, 2, ...
   const bool f32 = prec == RQ_MIXED_BF16;
   hipStream_t s = h->stream;
@@ -447,10 +451,10 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
                 (f32 ? 4.0 : 8.0) * (double)m * n + 8.0 * ((double)n * k + (double)m * k));
       if (f32)
         RQ_CHECK(h, launch_gemm_nn_bf16(Z1, m, (int)m, (int)k, static_cast<const float*>(A), lda, V,
-                                        ldv, (int)n, vbf, s));
+                                        ldv, (int)n, reinterpret_cast<__bf16*>(vstage), s));
       else
-        RQ_CHECK(h, launch_gemm_nn(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda, V, ldv,
-                                   (int)n, 1.0, 0.0, s));
+        RQ_CHECK(h, launch_gemm_nn_tall(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda,
+                                        V, ldv, (int)n, 1.0, vstage, s));
     }
     // 5. QR of Z1: U = Q[:, 0:k], X = upper factor
     RQ_TRY(qr_blocked(h, Z1, m, m, k, tauq, Tb2, w));
