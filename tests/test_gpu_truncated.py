@@ -70,6 +70,7 @@ def test_trqrcp_matches_oracle(api, m, n, k, b, p):
     (300, 240, 64, 32, 8),
     (400, 257, 100, 16, 8),
     (160, 300, 130, 64, 8),     # n > m, several 64-column QR panels
+    (700, 500, 300, 64, 8),     # k > 256: Z1 = A V in two column chunks
 ])
 def test_tuxv_matches_oracle(api, m, n, k, b, p):
     a = _case(m, n, 6100 + m, min(m, n) / 5.0)
