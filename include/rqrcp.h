@@ -44,7 +44,7 @@ enum {
   RQ_OK = 0,
   RQ_E_HIP = 1001,         /* a HIP runtime call failed                        */
   RQ_E_NOMEM = 1002,       /* workspace allocation failed                      */
-  RQ_E_UNSUPPORTED = 1003, /* valid arguments outside this build's limits      */
+  RQ_E_UNSUPPORTED = 1003, /* valid arguments outside the library's limits     */
   RQ_E_DEVICE = 1004       /* reported by rq_sync_status: see device_error bits */
 };
 
@@ -65,7 +65,7 @@ typedef enum {
 
 typedef struct rq_handle_s* rq_handle;
 
-/* Library limits of this build (checked by every entry point):
+/* Library limits (checked by every entry point):
  * 1 <= b <= 64, p >= 0, b + p <= 96, n <= 65536. */
 #define RQ_MAX_B 64
 #define RQ_MAX_ELL 96
