@@ -108,3 +108,18 @@ def test_rsrqrcp_bad_stride_rejected(api):
     rc = _lib.load().rsrqrcp_factor(h.ptr, m, n, n, b, p, A.data_ptr(), m, om.data_ptr(), b + p,
                                     (b + p) * m - 1, jp.data_ptr(), tau.data_ptr(), None, 0)
     assert rc == -11
+
+
+def test_rsrqrcp_parity_workload_1000(api):
+    """1000 x 1000, sigma_i = 10^(-i/100), b = 32, p = 8 (the parity workload)."""
+    cfg = synth.workload(0)
+    m, n, b, p = cfg["m"], cfg["n"], cfg["b"], cfg["p"]
+    sig = synth.spectrum("pow10", n, scale=100.0)
+    a = synth.low_rank(m, n, sig, synth.seed_for(0, "U"), synth.seed_for(0, "V"))
+    qr, jpvt, tau, T, ref = _run(api, a, b, p, n, synth.seed_for(0, "Omega") + 100)
+    pre = ref.trace.prefix(ref.sample_scale, REL, ABS)
+    assert pre >= 32, f"certified prefix only {pre}"
+    np.testing.assert_array_equal(jpvt[:pre], ref.jpvt[:pre])
+    q = q_from_inplace(qr, tau)
+    assert np.linalg.norm(a[:, jpvt] - q @ np.triu(qr)) / np.linalg.norm(a) <= 1e-13
+    print(f"certified pivot prefix {pre}/{n}")
