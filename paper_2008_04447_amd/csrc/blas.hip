@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void update_kernel(double* C, int64_t ldc, int
 // consecutive doubles; Y operands come straight from Y (16 consecutive rows per
 // 4 lanes).  Wave w owns columns 16 NBW w ..; the operands of the next two steps
 // are in flight (a ring of three register sets).  Rows at or past M are clamped
-// to row M - 1 and not stored; Z is zero past K and N.
+// to row M - 1 and not stored; Z is zero past K and N.  C = alpha Y Z + beta C.
 constexpr int kNf64Rows = 64;
 
 static int nf64_nbw(int N) { return N > 192 ? 4 : N > 128 ? 3 : N > 64 ? 2 : 1; }
@@ -681,7 +681,7 @@ template <int NBW>
 __global__ __launch_bounds__(256, 2) void gemm_nn_tall_kernel(double* C, int64_t ldc, int M, int N,
                                                               const double* Y, int64_t ldy,
                                                               const double* zt, int ncp, int K,
-                                                              double alpha) {
+                                                              double alpha, double beta) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kq = lane >> 4;
@@ -746,14 +746,17 @@ __global__ __launch_bounds__(256, 2) void gemm_nn_tall_kernel(double* C, int64_t
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = r0 + 16 * ib + kq + 4 * v;
-        if (r < M && c < N) C[r + (int64_t)c * ldc] = alpha * acc[ib][jb][v];
+        if (r < M && c < N) {
+          double* cp = C + r + (int64_t)c * ldc;
+          *cp = (beta != 0.0) ? alpha * acc[ib][jb][v] + beta * *cp : alpha * acc[ib][jb][v];
+        }
       }
     }
 }
 
 hipError_t launch_gemm_nn_tall(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
-                               const double* Z, int64_t ldz, int K, double alpha, double* zstage,
-                               hipStream_t s) {
+                               const double* Z, int64_t ldz, int K, double alpha, double beta,
+                               double* zstage, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (ldy < M || ldc < M || (K > 0 && !zstage)) return hipErrorInvalidValue;
   const int nbw = nf64_nbw(N), ncp = nf64_ncp(N);
@@ -766,10 +769,10 @@ hipError_t launch_gemm_nn_tall(double* C, int64_t ldc, int M, int N, const doubl
   }
   dim3 grid((M + kNf64Rows - 1) / kNf64Rows, ncp / (64 * nbw));
   switch (nbw) {
-    case 1: hipLaunchKernelGGL(gemm_nn_tall_kernel<1>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
-    case 2: hipLaunchKernelGGL(gemm_nn_tall_kernel<2>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
-    case 3: hipLaunchKernelGGL(gemm_nn_tall_kernel<3>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
-    default: hipLaunchKernelGGL(gemm_nn_tall_kernel<4>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha); break;
+    case 1: hipLaunchKernelGGL(gemm_nn_tall_kernel<1>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha, beta); break;
+    case 2: hipLaunchKernelGGL(gemm_nn_tall_kernel<2>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha, beta); break;
+    case 3: hipLaunchKernelGGL(gemm_nn_tall_kernel<3>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha, beta); break;
+    default: hipLaunchKernelGGL(gemm_nn_tall_kernel<4>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zstage, ncp, K, alpha, beta); break;
   }
   return hipGetLastError();
 }

@@ -108,13 +108,14 @@ hipError_t launch_reduce_t(const double* part, int64_t ldp, int64_t sstride, int
 // them (the units the launch may take beside concurrent persistent kernels).
 hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
                          const double* Z, int64_t ldz, int bj, int max_wgs, hipStream_t s);
-// C(M x N) = alpha Y(M x K) Z(K x N) for tall Y and small N (one pass over Y;
-// ldy, ldc >= M).  Z is first staged into zstage, which holds at least
-// gemm_nn_tall_stage_doubles(N, K) doubles (two kernels on stream s).
+// C(M x N) = alpha Y(M x K) Z(K x N) + beta C for tall Y and small N (one pass
+// over Y; ldy, ldc >= M; C is not read when beta == 0).  Z is first staged into
+// zstage, which holds at least gemm_nn_tall_stage_doubles(N, K) doubles (two
+// kernels on stream s).
 int64_t gemm_nn_tall_stage_doubles(int N, int K);
 hipError_t launch_gemm_nn_tall(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
-                               const double* Z, int64_t ldz, int K, double alpha, double* zstage,
-                               hipStream_t s);
+                               const double* Z, int64_t ldz, int K, double alpha, double beta,
+                               double* zstage, hipStream_t s);
 // C(M x N) = beta C + alpha Y(M x K) Z(K x N), any K (FP64 MFMA, 64 x 64 tiles).
 hipError_t launch_gemm_nn(double* C, int64_t ldc, int M, int N, const double* Y, int64_t ldy,
                           const double* Z, int64_t ldz, int K, double alpha, double beta,

@@ -137,9 +137,11 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
       KTimer kt(h, K_TR_SELECT, 2.0 * (double)M * bj * col0, 8.0 * (double)M * bj * 2.0);
       RQ_CHECK(h, launch_gather_cols(Av, f32, lda, (int)col0, jpvt + col0, w.awork, m, (int)M, bj,
                                      s));
+      // one pass over Y(col0:, 0:col0); W^T's columns are staged in the split-K
+      // buffer, free until this block's inner products
       if (col0 > 0)
-        RQ_CHECK(h, launch_gemm_nn(w.awork, m, (int)M, bj, Y + col0, ldy, w.wt + col0 * k, k,
-                                   (int)col0, -1.0, 1.0, s));
+        RQ_CHECK(h, launch_gemm_nn_tall(w.awork, m, (int)M, bj, Y + col0, ldy, w.wt + col0 * k, k,
+                                        (int)col0, -1.0, 1.0, w.part, s));
     }
     // 4. panel QR of the selected block: Y2, T2, R11
     double* tau_scratch = w.mhat;   // tau values also sit on the diagonal of T2
@@ -454,7 +456,7 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
                                         ldv, (int)n, reinterpret_cast<__bf16*>(vstage), s));
       else
         RQ_CHECK(h, launch_gemm_nn_tall(Z1, m, (int)m, (int)k, static_cast<const double*>(A), lda,
-                                        V, ldv, (int)n, 1.0, vstage, s));
+                                        V, ldv, (int)n, 1.0, 0.0, vstage, s));
     }
     // 5. QR of Z1: U = Q[:, 0:k], X = upper factor
     RQ_TRY(qr_blocked(h, Z1, m, m, k, tauq, Tb2, w));
