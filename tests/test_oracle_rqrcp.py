@@ -1,6 +1,7 @@
 """Pins of the oracle's RQRCP (Algorithm 4), RSRQRCP and single-sample RQRCP.
 
-* Omega = I with ell = m reduces RQRCP to textbook QRCP (pivots identical).
+* Omega = I with ell = m reduces RQRCP to textbook QRCP (pivots identical), and
+  identity samples of every trailing matrix do the same for RSRQRCP.
 * The sample update formula equals an explicit re-projection of the trailing
   matrix with Omega^[J] = (U^T Omega^[J-1] Q)(:, b+1:), and the lower-left block of
   U^T Omega Q vanishes (Section 3.2 and eq. sample / sampleR).
@@ -135,6 +136,24 @@ def test_rsrqrcp_first_block_and_invariants():
     np.testing.assert_array_equal(res.jpvt[:b], one.jpvt[:b])
     q = q_from_inplace(res.qr, res.tau)
     assert np.linalg.norm(a[:, res.jpvt] - q @ np.triu(res.qr)) / np.linalg.norm(a) <= 1e-13
+
+
+def test_rsrqrcp_identity_samples_reduce_to_qrcp():
+    """With ell >= m and every Omega^[J] the first rows of the identity, each
+    block's fresh sample is the trailing matrix itself padded with zero rows, so
+    every block (not only the first) picks textbook QRCP's pivots."""
+    m, n, b, p = 24, 40, 4, 20
+    sig = synth.spectrum("pow10", 24, scale=8.0)
+    a = synth.low_rank(m, n, sig, 121, 122)
+
+    def omegas(j, rows):
+        return np.eye(b + p, rows)
+
+    res = oracle.rsrqrcp(a, omegas, b, p, k=20)
+    ref = oracle.qrcp(a, k=20)
+    np.testing.assert_array_equal(res.jpvt[:20], ref.jpvt[:20])
+    np.testing.assert_allclose(np.abs(np.triu(res.qr[:20])), np.abs(np.triu(ref.qr[:20])),
+                               rtol=1e-10, atol=1e-12)
 
 
 def test_single_sample_equals_one_block_rqrcp():
