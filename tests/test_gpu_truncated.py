@@ -1,4 +1,5 @@
-"""GPU parity of TRQRCP (Algorithm 5) and TUXV (Algorithm 6) against the FP64 oracle.
+"""GPU parity of TRQRCP (Algorithm 5), single-sample RQRCP (Algorithm 3) and TUXV
+(Algorithm 6) against the FP64 oracle.
 
 Pivots must match the oracle exactly on the certified prefix (sample norms
 recomputed exactly on both sides); Y, T and R to 1e-10 relative plus an
@@ -64,6 +65,32 @@ def test_trqrcp_matches_oracle(api, m, n, k, b, p):
     err_gpu = np.linalg.norm(ap - q[:, :k] @ R)
     ref_err = np.linalg.norm(a[:, ref.jpvt] - (np.eye(m) - ref.y @ ref.t @ ref.y.T)[:, :k] @ ref.r)
     assert err_gpu <= ref_err * (1 + 1e-8) + 1e-13 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("m,n,k,p", [
+    (300, 240, 24, 8),
+    (513, 200, 64, 16),         # b = k at the library's limit, ragged m
+    (150, 400, 7, 5),           # n > m, k not a multiple of 4
+])
+def test_single_sample_rqrcp_matches_oracle(api, m, n, k, p):
+    """Algorithm 3 (one sample of ell = k + p rows, k pivots) is TRQRCP with b = k."""
+    a = _case(m, n, 6500 + m, min(m, n) / 5.0)
+    om = synth.omega(k + p, m, 6502 + n)
+    jpvt, Y, T, R = api.trqrcp_truncate(_dev(api, a), _dev(api, om), k, p, k)
+    api.default_handle(0).sync()
+    jpvt, Y, R = (x.cpu().numpy() for x in (jpvt, Y, R))
+    w, tau, ref_jpvt, trace = oracle.single_sample_rqrcp(a, om, k)
+    pre = trace.prefix(np.linalg.norm(om @ a, axis=0).max(), REL, ABS)
+    assert pre >= min(k, 8)
+    assert sorted(jpvt) == list(range(n))
+    np.testing.assert_array_equal(jpvt[:pre], ref_jpvt[:pre])
+    ref_r = np.triu(w[:k])
+    floor = 1e-12 * np.linalg.norm(a)
+    d = np.linalg.norm(R[:pre] - ref_r[:pre], axis=1)
+    assert np.all(d <= 1e-10 * np.linalg.norm(ref_r[:pre], axis=1) + floor)
+    if pre >= k:
+        np.testing.assert_array_equal(jpvt, ref_jpvt)
+        np.testing.assert_allclose(Y, np.tril(w[:, :k], -1) + np.eye(m, k), atol=1e-9)
 
 
 @pytest.mark.parametrize("m,n,k,b,p", [
