@@ -112,6 +112,10 @@ const char* rq_last_error(rq_handle h);
  *  T, ldt    out: b x k block-T (like dgeqrt): for the block starting at column
  *            c0 with width bJ, T[0:bJ, c0:c0+bJ] is upper triangular with
  *            H_c0 ... H_{c0+bJ-1} = I - Y_J T_J Y_J^T.  ldt >= b.  May be NULL.
+ * The sample update divides by R11: an exactly singular R11 (say a block of
+ * all-zero columns) makes the updated sample non-finite, which is reported as
+ * RQ_DEV_NONFINITE / RQ_DEV_NO_PIVOT and leaves the later blocks unpivoted;
+ * rsrqrcp_factor needs no R11^{-1}.
  * Argument numbers for errors: h=1 m=2 n=3 k=4 b=5 p=6 A=7 lda=8 Omega=9
  * ldo=10 jpvt=11 tau=12 T=13 ldt=14.
  */
@@ -234,7 +238,10 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
  * position), with every column transformed.  On exit B holds
  * [[S11, S12], [0, S22]] in pivoted column order (zeros below the diagonal of
  * the first `steps` columns), and perm[j] (j < n) is the input position of
- * the column now at position j.
+ * the column now at position j.  A NaN or infinite column never becomes a
+ * pivot and sets RQ_DEV_NONFINITE; when no column is left that can be chosen
+ * the pivoting stops with RQ_DEV_NO_PIVOT, B keeps its input and perm the
+ * identity.  Either bit makes rq_sync_status return RQ_E_DEVICE.
  * Argument numbers: h=1 ell=2 n=3 steps=4 B=5 ldb=6 perm=7.
  */
 rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, double* B,

@@ -434,10 +434,9 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
   w.rec = cv.take<double>(sq_rec_doubles((int)ell, n));
   w.src_top = cv.take<int>(64);
   w.dst_low = cv.take<int>(64);
-  if (steps == 0) {
-    RQ_CHECK(h, launch_iota(perm, (int)n, h->stream));
-    return RQ_OK;
-  }
+  // identity first: a pivoting that stops early (no admissible column) leaves it
+  RQ_CHECK(h, launch_iota(perm, (int)n, h->stream));
+  if (steps == 0) return RQ_OK;
   return run_sample_qrcp(h, B, ldb, (int)ell, n, (int)steps, w, perm);
 }
 
@@ -563,8 +562,8 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     // 2. permute all m rows of A's columns col0.. (finished R rows included), jpvt
     {
       KTimer kt(h, K_PERMUTE, 0.0, 32.0 * bj * (double)m);
-      RQ_CHECK(h, launch_permute(A + col0 * lda, lda, (int)m, bj, sw.src_top, sw.dst_low,
-                                 jpvt + col0, s));
+      RQ_CHECK(h, launch_permute(A + col0 * lda, lda, (int)m, bj, n - col0, sw.src_top,
+                                 sw.dst_low, jpvt + col0, s));
     }
     // 3. panel QR of the b selected columns and T of the block (written straight
     // into the caller's T when there is one: only its bj x bj block is touched)

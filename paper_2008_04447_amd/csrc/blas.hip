@@ -950,14 +950,27 @@ hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int
 // reads every moved value of that row into registers (all loads in flight at
 // once), then, after the workgroup's barrier, writes them: the only reads a
 // write could clobber are those of the same slab, and slabs are disjoint.
+//
+// The block has ncols columns.  A sample QRCP that stopped early (non-finite
+// norms, an expired wait: both leave a status bit) does not write the maps, so
+// entries are checked here: a source outside 0..ncols-1 leaves its column in
+// place and a destination outside bj..ncols-1 moves nothing.  Every access
+// stays inside the block whatever the maps hold.
 __global__ __launch_bounds__(256) void permute_kernel(double* X, int64_t ldx, int rows, int bj,
-                                                      const int* src_top, const int* dst_low,
-                                                      int64_t* jpvt) {
+                                                      int ncols, const int* src_top,
+                                                      const int* dst_low, int64_t* jpvt) {
   __shared__ int s_src[64], s_dst[64];
   const int t = threadIdx.x;
   if (t < 64) {
-    s_src[t] = (t < bj) ? src_top[t] : -1;
-    s_dst[t] = (t < bj) ? dst_low[t] : -1;
+    int sv = -1, dv = -1;
+    if (t < bj) {
+      sv = src_top[t];
+      dv = dst_low[t];
+      if (sv < 0 || sv >= ncols) sv = t;
+      if (dv < bj || dv >= ncols) dv = -1;
+    }
+    s_src[t] = sv;
+    s_dst[t] = dv;
   }
   __syncthreads();
   const int r = blockIdx.x * 64 + (t & 63);
@@ -993,11 +1006,12 @@ __global__ __launch_bounds__(256) void permute_kernel(double* X, int64_t ldx, in
   }
 }
 
-hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, const int* src_top,
-                          const int* dst_low, int64_t* jpvt, hipStream_t s) {
+hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, int64_t ncols,
+                          const int* src_top, const int* dst_low, int64_t* jpvt, hipStream_t s) {
+  if (bj < 0 || bj > 64 || ncols < bj || ncols > INT_MAX) return hipErrorInvalidValue;
   const int blocks = rows > 0 ? (rows + 63) / 64 : 1;
-  hipLaunchKernelGGL(permute_kernel, dim3(blocks), dim3(256), 0, s, X, ldx, rows, bj, src_top,
-                     dst_low, jpvt);
+  hipLaunchKernelGGL(permute_kernel, dim3(blocks), dim3(256), 0, s, X, ldx, rows, bj, (int)ncols,
+                     src_top, dst_low, jpvt);
   return hipGetLastError();
 }
 

@@ -146,9 +146,11 @@ hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int
                           int bj, double* M, int64_t ldm, hipStream_t s);
 
 // Column permutation of `rows` x (cols col0..) of X given by src_top/dst_low,
-// plus the same permutation of jpvt (int64, may be null).
-hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, const int* src_top,
-                          const int* dst_low, int64_t* jpvt, hipStream_t s);
+// plus the same permutation of jpvt (int64, may be null).  ncols = columns of
+// the block (X and jpvt hold at least that many); map entries outside it move
+// nothing.
+hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, int64_t ncols,
+                          const int* src_top, const int* dst_low, int64_t* jpvt, hipStream_t s);
 
 hipError_t launch_iota(int64_t* v, int n, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s);

@@ -126,11 +126,11 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
     // 2. permute the index map, W^T and the finished R rows (A is not moved)
     {
       KTimer kt(h, K_PERMUTE, 0.0, 32.0 * bj * (double)(2 * col0 + 1));
-      RQ_CHECK(h, launch_permute(w.wt + col0 * k, k, (int)col0, bj, w.sw.src_top, w.sw.dst_low,
-                                 jpvt + col0, s));
+      RQ_CHECK(h, launch_permute(w.wt + col0 * k, k, (int)col0, bj, N, w.sw.src_top,
+                                 w.sw.dst_low, jpvt + col0, s));
       if (col0 > 0)
-        RQ_CHECK(h, launch_permute(R + col0 * ldr, ldr, (int)col0, bj, w.sw.src_top, w.sw.dst_low,
-                                   nullptr, s));
+        RQ_CHECK(h, launch_permute(R + col0 * ldr, ldr, (int)col0, bj, N, w.sw.src_top,
+                                   w.sw.dst_low, nullptr, s));
     }
     // 3. selected columns of A - Y W^T, rows col0..m-1
     {

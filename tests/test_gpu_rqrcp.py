@@ -69,6 +69,31 @@ def test_sample_qrcp_matches_oracle(api, ell, n, steps):
         np.testing.assert_allclose(s, ref.s, atol=1e-12 * scale)
 
 
+def test_sample_qrcp_nonfinite_is_reported(api):
+    """A NaN column never becomes a pivot and sets the non-finite bit; an
+    all-NaN sample stops with no admissible pivot, leaving B and the identity
+    permutation.  The next sync reports the bits and clears them."""
+    ell, n, steps = 16, 300, 8
+    h = api.default_handle(0)
+    b = synth.gaussian((ell, n), 3100)
+    b[:, 7] = np.nan
+    perm = api.sample_qrcp(_dev(api, b), steps)
+    with pytest.raises(api.RQError, match="bits = 2$"):
+        h.sync()
+    g = _host(perm)
+    assert sorted(g) == list(range(n)) and 7 not in g[:steps]
+    B = _dev(api, np.full((ell, n), np.nan))
+    perm = api.sample_qrcp(B, steps)
+    with pytest.raises(api.RQError, match="bits = 6$"):
+        h.sync()
+    np.testing.assert_array_equal(_host(perm), np.arange(n))
+    assert np.isnan(_host(B)).all()
+    # the status word was cleared: a finite sample runs clean again
+    b = synth.gaussian((ell, n), 3101)
+    api.sample_qrcp(_dev(api, b), steps)
+    h.sync()
+
+
 # ----------------------------------------------------------------------------- RQRCP
 def _rqrcp_case(api, m, n, b, p, k, a, om):
     A = _dev(api, a)
