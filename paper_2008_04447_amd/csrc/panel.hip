@@ -449,7 +449,6 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
 
   // LDS: four 64 x 64 regions shared by the two routes, plus small vectors
   __shared__ double s_reg[4][kRegion];
-  __shared__ double s_bc[2][kPanelRows];   // column j (before its reflection), by step parity
   __shared__ double s_vec[5][kPC];
   double* const s_tau = s_vec[0];
   double (*const s_T)[kLd] = reinterpret_cast<double (*)[kLd]>(s_reg[1]);
