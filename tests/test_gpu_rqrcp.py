@@ -198,6 +198,22 @@ def test_rqrcp_zero_rank_and_empty(api):
     np.testing.assert_array_equal(_host(jpvt), np.arange(n))
 
 
+def test_rqrcp_singular_r11_is_reported(api):
+    """An all-zero matrix factored past its first block: R11 = 0, so the sample
+    update of eq. (update1) turns the sample into NaNs.  Later sample QRCPs stop
+    with no admissible pivot; the status bits report it, every access stays in
+    bounds (the column maps left from block 0 are checked) and the zero factor
+    is untouched: no column moves and every tau is zero."""
+    m, n, b, p = 120, 90, 16, 8
+    A = _dev(api, np.zeros((m, n)))
+    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, synth.omega(b + p, m, 2)), b, p, k=n)
+    with pytest.raises(api.RQError, match="bits = 6$"):
+        api.default_handle(0).sync()
+    np.testing.assert_array_equal(_host(jpvt), np.arange(n))
+    assert np.all(_host(tau) == 0.0)
+    assert np.all(_host(A) == 0.0)
+
+
 def test_rqrcp_deterministic(api):
     m, n, b, p = 400, 380, 32, 8
     a = synth.gaussian((m, n), 4300)

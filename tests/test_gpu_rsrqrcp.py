@@ -96,6 +96,20 @@ def test_rsrqrcp_first_block_equals_rqrcp(api):
     np.testing.assert_array_equal(tau[:b], _host(tau2)[:b])
 
 
+def test_rsrqrcp_zero_matrix_runs_clean(api):
+    """Repeated sampling needs no R11^{-1}: the all-zero matrix whose sample
+    update breaks down in RQRCP factors without a status bit, with no column
+    moved and every tau zero."""
+    m, n, b, p = 120, 90, 16, 8
+    _, om = _omegas(b + p, m, (n + b - 1) // b, 4800)
+    A = api.colmajor(np.zeros((m, n)), device=torch.device("cuda", 0))
+    jpvt, tau, T = api.rsrqrcp_factor(A, om, b, p, n)
+    api.default_handle(0).sync()
+    np.testing.assert_array_equal(_host(jpvt), np.arange(n))
+    assert np.all(_host(tau) == 0.0)
+    assert np.all(_host(A) == 0.0)
+
+
 def test_rsrqrcp_bad_stride_rejected(api):
     m, n, b, p = 64, 48, 16, 4
     a = synth.gaussian((m, n), 4700)
