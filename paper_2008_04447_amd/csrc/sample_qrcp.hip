@@ -284,9 +284,11 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
           d0 += vi * x[i];
       }
       const double d = tau * column_sum<kQ>(d0 + d1);
-      // the vector is read from LDS again rather than held in registers across
-      // the reduction (the empty asm keeps the compiler from reusing the reads)
-      asm volatile("" ::: "memory");
+      // 512-thread workgroups keep the vector's values in registers across the
+      // reduction (one batch of LDS reads per step).  At 1024 threads (128
+      // registers per lane) that would spill, so there the vector is read from
+      // LDS again; the empty asm keeps the compiler from reusing the reads.
+      if constexpr (NT >= 1024) asm volatile("" ::: "memory");
       double n0 = 0.0, n1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
