@@ -15,7 +15,7 @@ wall time of that step as `profiled_ms_per_step`) and its longest kernel class
 is the one the roofline covers.  The timed steps bracket only that class with
 events (two per launch), since events around every launch add device time of
 their own; the plain QRCP comparator and the repeated-sampling RQRCP
-(Section 3.2: a fresh sketch of each trailing matrix instead of the sample
+(Section 3.4: a fresh sketch of each trailing matrix instead of the sample
 update) are timed with no events at all.
 
 Prints progress on stderr and one JSON line on stdout.
@@ -270,7 +270,7 @@ def bench_rqrcp(args):
 
     resampled = None
     if not args.no_resample:
-        # RQRCP with repeated sampling (Section 3.2) on the same matrix: each block
+        # RQRCP with repeated sampling (Section 3.4) on the same matrix: each block
         # sketches its updated trailing matrix with a fresh Omega instead of the
         # sample update (slice 0 is the Omega above, so block 0 is the same)
         nblk = (n + b - 1) // b

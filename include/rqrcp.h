@@ -124,7 +124,7 @@ rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, 
                        int64_t* jpvt, double* tau, double* T, int64_t ldt);
 
 /*
- * rsrqrcp_factor -- RQRCP with repeated sampling (Section 3.2): Algorithm 4
+ * rsrqrcp_factor -- RQRCP with repeated sampling (Section 3.4): Algorithm 4
  * with the sample update replaced by a fresh sample of the trailing matrix,
  * B^[J] = Omega^[J] A^[J], after each block's trailing update.  It is the
  * baseline the sample update formula is measured against (one more pass over

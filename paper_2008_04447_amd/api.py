@@ -121,7 +121,7 @@ def rqrcp_factor(A, Omega, b, p, k=None, handle=None):
 
 
 def rsrqrcp_factor(A, Omegas, b, p, k=None, handle=None):
-    """RQRCP with repeated sampling (Section 3.2) in place on A.
+    """RQRCP with repeated sampling (Section 3.4) in place on A.
 
     Omegas is a float64 device tensor of ceil(k / b) column-major ell x m
     slices (shape (nblk, m, ell) with unit stride along ell, i.e. slice J is

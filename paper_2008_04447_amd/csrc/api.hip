@@ -443,7 +443,7 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
 }  // extern "C"
 
 // The block loop of Algorithm 4.  With `resample` (repeated sampling, Section
-// 3.2) the sample of block J is a fresh sketch of the updated trailing matrix,
+// 3.4) the sample of block J is a fresh sketch of the updated trailing matrix,
 // B = Omega^[J] A^[J], with Omega^[J] the first m - Jb columns of the ell x m
 // slice Omega + J ostride, instead of the sample update (eq. update1).
 static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,

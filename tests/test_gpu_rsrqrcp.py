@@ -1,4 +1,4 @@
-"""GPU parity of RQRCP with repeated sampling (Section 3.2: the sample of block
+"""GPU parity of RQRCP with repeated sampling (Section 3.4: the sample of block
 J is a fresh sketch Omega^[J] A^[J] of the updated trailing matrix instead of
 the sample update) against the FP64 oracle, to the bar of the RQRCP tests:
 pivots equal on the certified prefix, R rows to 1e-10 relative there, and the

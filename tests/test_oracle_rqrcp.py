@@ -4,7 +4,7 @@
   identity samples of every trailing matrix do the same for RSRQRCP.
 * The sample update formula equals an explicit re-projection of the trailing
   matrix with Omega^[J] = (U^T Omega^[J-1] Q)(:, b+1:), and the lower-left block of
-  U^T Omega Q vanishes (Section 3.2 and eq. sample / sampleR).
+  U^T Omega Q vanishes (Sections 3.2 and 3.4, eq. sample / sampleR).
 * Invariants of any column-pivoted Householder QR.
 * The Gaussian sketch moments E||Omega a||^2 = ell ||a||^2, Var = 2 ell ||a||^4
   (Section 3) and the posterior CDF values printed with Figure 1.
