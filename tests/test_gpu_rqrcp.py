@@ -181,6 +181,62 @@ def test_rqrcp_config_1000(api):
     print(f"certified pivot prefix {pre}/{n}")
 
 
+def test_rqrcp_headline_8000_sampled_parity(api):
+    """8000 x 8000 N(0,1), b = 64, p = 8, in the launch configuration the
+    benchmark times.  Sampled outputs that the oracle computes directly: the
+    first block (Algorithm 3 with k = b on the same Omega) fixes the first b
+    pivots and R's first b rows.  Properties at full size, with FP64 products
+    on the device: ||AP - QR||_F / ||A||_F and Q^T Q = I on random vectors."""
+    m = n = 8000
+    b, p = 64, 8
+    a = synth.gaussian((m, n), synth.seed_for(1, "U"))
+    om = synth.omega(b + p, m, synth.seed_for(1, "Omega"))
+    A = _dev(api, a)
+    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, om), b, p)
+    api.default_handle(0).sync()
+    jp = _host(jpvt)
+    assert np.array_equal(np.sort(jp), np.arange(n))
+    # the first block from the oracle
+    w, tau1, ref_jp, trace = oracle.single_sample_rqrcp(a, om, b)
+    pre = trace.prefix(np.linalg.norm(om @ a, axis=0).max(), REL, ABS)
+    assert pre >= 16
+    np.testing.assert_array_equal(jp[:pre], ref_jp[:pre])
+    where = np.empty(n, dtype=np.int64)
+    where[ref_jp] = np.arange(n)                  # oracle position of each input column
+    r_top = np.triu(_host(A[:pre]))
+    r_ref = np.triu(w[:pre])[:, where[jp]]        # same input columns, GPU order
+    floor = 1e-12 * np.linalg.norm(a)
+    d = np.linalg.norm(r_top - r_ref, axis=1)
+    assert np.all(d <= 1e-10 * np.linalg.norm(r_ref, axis=1) + floor)
+    if pre == b:
+        np.testing.assert_allclose(_host(tau[:b]), tau1, rtol=1e-10, atol=1e-14)
+    # full-size properties: Q = prod_J (I - Y_J T_J Y_J^T) applied block by block
+    dev = A.device
+    qr = A
+    tdev = T
+
+    def apply_q(x, transpose):
+        blocks = range(0, n, b) if transpose else reversed(range(0, n, b))
+        for c0 in blocks:
+            y = torch.tril(qr[c0:, c0:c0 + b], -1)
+            y.diagonal().fill_(1.0)
+            t = tdev[:b, c0:c0 + b]
+            yt = y.t().contiguous()
+            z = (t.t().contiguous() if transpose else t) @ (yt @ x[c0:])
+            x[c0:] -= y @ z
+        return x
+
+    r_full = torch.triu(qr)
+    prod = apply_q(r_full.clone(), transpose=False)
+    ap = _dev(api, a)[:, torch.from_numpy(jp).to(dev)]
+    rel = (torch.linalg.norm(ap - prod) / torch.linalg.norm(ap)).item()
+    print(f"8000^2: certified prefix {pre}/{b}, ||AP - QR||/||A|| = {rel:.2e}")
+    assert rel <= 1e-13
+    g = torch.from_numpy(synth.gaussian((m, 16), 4400)).to(dev)
+    back = apply_q(apply_q(g.clone(), transpose=True), transpose=False)
+    assert (torch.linalg.norm(back - g) / torch.linalg.norm(g)).item() <= 1e-13
+
+
 def test_rqrcp_known_pivot_family_full_parity(api):
     """Steeply graded columns: every sample decision is certified."""
     m, n, b, p = 200, 120, 16, 8
