@@ -109,3 +109,40 @@ def test_tuxv_iter_jmax_is_argument_19(lib):
     args = (0, 10, 8, 4, 2, 2, buf, 10, buf, 4, buf, 10, buf, 4, buf, 8, buf)
     assert lib.tuxv_svd_iter(None, *args, 1) == -1
     assert lib.tuxv_svd_iter(FAKE, *args, 0) == -19
+
+
+def _declared_params():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:rq_status|const char\*|int32_t)\s+(\w+)\s*\((.*?)\);", text,
+                         flags=re.M | re.S):
+        params = [" ".join(p.split()) for p in m.group(2).split(",") if p.strip()]
+        out[m.group(1)] = [p.rsplit(" ", 1)[0] for p in params]
+    return out
+
+
+def _kind_of_c(t):
+    if "*" in t or t in ("rq_handle", "rq_server"):
+        return "ptr"
+    return {"int64_t": "i64", "uint64_t": "u64", "int32_t": "i32", "int": "i32", "rq_prec": "i32",
+            "uint32_t": "u32", "size_t": "u64", "double": "f64"}[t]
+
+
+def _kind_of_ctypes(t):
+    import ctypes
+    if t in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(t, "_type_") and t.__name__.startswith("LP_"):
+        return "ptr"
+    return {ctypes.c_int64: "i64", ctypes.c_uint64: "u64", ctypes.c_int32: "i32",
+            ctypes.c_uint32: "u32", ctypes.c_double: "f64"}[t]
+
+
+def test_binding_signatures_match_the_header():
+    """Every ctypes signature has the header's parameter count and kinds, so a
+    change on one side cannot silently shift the arguments of the other."""
+    from paper_2008_04447_amd import _lib
+    decl = _declared_params()
+    assert set(_lib.SIGNATURES) <= set(decl)
+    for name, (_, argtypes) in _lib.SIGNATURES.items():
+        want = [_kind_of_c(t.replace("const ", "")) for t in decl[name]]
+        got = [_kind_of_ctypes(t) for t in argtypes]
+        assert got == want, name
