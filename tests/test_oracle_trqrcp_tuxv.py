@@ -106,3 +106,28 @@ def test_tuxv_second_iteration_runs_and_is_lower_triangular():
     e1 = np.linalg.norm(a - r1.u @ r1.x @ r1.v.T)
     e2 = np.linalg.norm(a - r2.u @ r2.x @ r2.v.T)
     assert e2 <= e1 * (1 + 1e-10)
+
+
+def test_tuxv_alternations_converge_to_the_truncated_svd():
+    """Each alternation of Algorithm 6 is one step of subspace iteration.
+    After an odd number of steps U X V^T = A V V^T, and after an even number it
+    is U U^T A.  Each is the best approximation in a subspace that contains the
+    previous one, so the error never grows.  With a gap sigma_{k+1} / sigma_k = 0.1
+    it reaches the Eckart-Young optimum geometrically."""
+    m, n, k, b, p = 90, 70, 12, 8, 6
+    sig = np.concatenate([np.linspace(1.0, 0.5, k), 0.05 * np.linspace(1.0, 0.1, min(m, n) - k)])
+    a = synth.low_rank(m, n, sig, 410, 411)
+    om = synth.omega(b + p, m, 412)
+    opt = np.sqrt(np.sum(sig[k:] ** 2))
+    excess = []
+    for jmax in range(1, 7):
+        r = oracle.tuxv(a, om, b, p, k, jmax=jmax)
+        approx = r.u @ r.x @ r.v.T
+        closed = a @ r.v @ r.v.T if jmax % 2 else r.u @ (r.u.T @ a)
+        np.testing.assert_allclose(approx, closed, atol=1e-13)
+        tri = np.triu(r.x) if jmax % 2 else np.tril(r.x)
+        np.testing.assert_array_equal(r.x, tri)
+        excess.append(np.linalg.norm(a - approx) / opt - 1.0)
+    assert excess[0] > 1e-4                        # one pass is visibly short of optimal
+    assert all(e2 <= e1 + 1e-14 for e1, e2 in zip(excess, excess[1:]))
+    assert excess[-1] <= 1e-9
