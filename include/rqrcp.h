@@ -66,7 +66,11 @@ typedef enum {
 typedef struct rq_handle_s* rq_handle;
 
 /* Library limits (checked by every entry point):
- * 1 <= b <= 64, p >= 0, b + p <= 96, n <= 65536. */
+ * 1 <= b <= 64, p >= 0, b + p <= 96, n <= 65536.  The persistent kernels put
+ * one workgroup of 256 rows (or sample columns) on each compute unit, all
+ * resident at once, so a factorization also needs max(m, n) <= 256 x the
+ * device's compute units (65536 on MI355X); larger valid sizes return
+ * RQ_E_UNSUPPORTED before anything is enqueued. */
 #define RQ_MAX_B 64
 #define RQ_MAX_ELL 96
 #define RQ_MAX_N 65536

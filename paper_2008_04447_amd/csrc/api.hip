@@ -284,8 +284,10 @@ rq_status rq_create(rq_handle* out, int device, void* hip_stream) {
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
-      cus > 0)
+      cus > 0) {
     h->update_wgs = cus;
+    h->cus = cus;
+  }
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->status), 4 * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->sync), 64 * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->status, 0, 4 * sizeof(int64_t), h->stream);
@@ -427,6 +429,7 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
   if (ldb < ell) return -6;
   if (!valid_ptr(perm, n)) return -7;
   if (n == 0) return RQ_OK;
+  if (steps > 0 && !rows_fit(h, n)) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
   RQ_TRY(reserve(h, padded_bytes(sq_rec_doubles((int)ell, n)) + 2 * 64 * sizeof(int) + 512));
   Carve cv(h->ws);
@@ -467,6 +470,7 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
   if (!valid_ptr(tau, k)) return -12;
   if (T && ldt < b) return -14;
   if (n == 0) return RQ_OK;
+  if (k > 0 && !rows_fit(h, std::max(m, n))) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
   hipStream_t s = h->stream;
   if (k == 0) {

@@ -63,6 +63,7 @@ struct rq_handle_s {
   uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag
   int max_groups = 128;        // workgroups one persistent sample-QRCP launch may use
   int update_wgs = 256;        // compute units a trailing-update launch may fill (device count)
+  int cus = 256;               // compute units of the device
   hipStream_t side = nullptr;  // second stream of the RQRCP block loop (created on first use)
   hipEvent_t ev_z = nullptr, ev_u = nullptr;
   std::string last_error;
@@ -73,6 +74,13 @@ struct rq_handle_s {
   size_t pool_used = 0;
   rq::ProfTot tot[rq::K_NUM_CLASSES];
 };
+
+// The persistent kernels (panels, plain-QRCP steps) give each workgroup
+// kPanelRows rows, one workgroup per compute unit, and need all of them
+// resident at once: m rows fit when ceil(m / kPanelRows) <= compute units.
+inline bool rows_fit(const rq_handle_s* h, int64_t m) {
+  return (m + rq::kPanelRows - 1) / rq::kPanelRows <= h->cus;
+}
 
 namespace rq {
 

@@ -316,6 +316,7 @@ extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, i
   if (!valid_ptr(jpvt, n)) return -8;
   if (!valid_ptr(tau, k)) return -9;
   if (n == 0) return RQ_OK;
+  if (k > 0 && !rows_fit(h, std::max(m, n))) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
   hipStream_t s = h->stream;
   RQ_CHECK(h, launch_iota(jpvt, (int)n, s));

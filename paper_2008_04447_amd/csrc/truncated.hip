@@ -384,6 +384,7 @@ extern "C" rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64
   if (!valid_ptr(R, k * n)) return -17;
   if (ldr < std::max<int64_t>(1, k)) return -18;
   if (n == 0) return RQ_OK;
+  if (k > 0 && !rows_fit(h, std::max(m, n))) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
   if (k == 0) {
     RQ_CHECK(h, launch_iota(jpvt, (int)n, h->stream));
@@ -416,6 +417,7 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
     if (n > 0) RQ_CHECK(h, launch_iota(jpvt, (int)n, h->stream));
     return RQ_OK;
   }
+  if (!rows_fit(h, std::max(m, n))) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
   const int ell = (int)(b + p);
   // TRQRCP state (Y, T, R) plus the two QR work arrays live in the workspace.
