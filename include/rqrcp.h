@@ -69,8 +69,8 @@ typedef struct rq_handle_s* rq_handle;
  * 1 <= b <= 64, p >= 0, b + p <= 96, n <= 65536.  The persistent kernels put
  * one workgroup of 256 rows (or sample columns) on each compute unit, all
  * resident at once, so a factorization also needs max(m, n) <= 256 x the
- * device's compute units (65536 on MI355X); larger valid sizes return
- * RQ_E_UNSUPPORTED before anything is enqueued. */
+ * device's compute units (65536 on MI355X), and rq_sketch needs m < 2^31;
+ * larger valid sizes return RQ_E_UNSUPPORTED before anything is enqueued. */
 #define RQ_MAX_B 64
 #define RQ_MAX_ELL 96
 #define RQ_MAX_N 65536

@@ -404,6 +404,7 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
   if (!valid_ptr(B, ell * n)) return -10;
   if (ldb < ell) return -11;
   if (n == 0) return RQ_OK;
+  if (m > INT_MAX) return RQ_E_UNSUPPORTED;   // the products index rows with 32-bit ints
   DeviceGuard guard(h->device);
   const size_t np = std::max(sketch_part_doubles((int)ell, m, n),
                              sketch_part_doubles_bf16((int)ell, m, n));
