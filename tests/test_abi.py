@@ -146,3 +146,14 @@ def test_binding_signatures_match_the_header():
         want = [_kind_of_c(t.replace("const ", "")) for t in decl[name]]
         got = [_kind_of_ctypes(t) for t in argtypes]
         assert got == want, name
+
+
+@pytest.mark.parametrize("cmd", [["gcc", "-std=c99", "-x", "c"], ["g++", "-std=c++17", "-x", "c++"]])
+def test_header_compiles_standalone(cmd):
+    """include/rqrcp.h is plain C: it compiles on its own as C99 and as C++."""
+    import shutil
+    if shutil.which(cmd[0]) is None:
+        pytest.skip(f"{cmd[0]} not installed")
+    r = subprocess.run(cmd[:1] + ["-fsyntax-only", "-Wall", "-Wextra", "-Werror"] + cmd[1:] + [HEADER],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
