@@ -19,8 +19,7 @@ inputs and theorems that bound QRCP's diagonal.  The per-step pivot evidence is
 reported through ``PivotTrace`` so parity tests can restrict exact pivot
 comparison to well-separated decisions.
 """
-from .householder import (apply_qt, form_q, form_t, householder_qr, reflector,
-                          unit_lower, upper)
+from .householder import form_q, form_t, householder_qr, reflector, unit_lower
 from .qrcp import (PivotTrace, QRCPResult, SampleQRCP, apply_transpositions,
                    partial_qrcp, qrcp, qrcp_inplace)
 from .rqrcp import RQRCPResult, rqrcp, rsrqrcp, sample_update, single_sample_rqrcp
@@ -28,7 +27,7 @@ from .trqrcp import TRQRCPResult, trqrcp
 from .tuxv import TUXVResult, tuxv
 
 __all__ = [
-    "apply_qt", "form_q", "form_t", "householder_qr", "reflector", "unit_lower", "upper",
+    "form_q", "form_t", "householder_qr", "reflector", "unit_lower",
     "PivotTrace", "QRCPResult", "SampleQRCP", "apply_transpositions", "partial_qrcp",
     "qrcp", "qrcp_inplace", "RQRCPResult", "rqrcp", "rsrqrcp", "sample_update",
     "single_sample_rqrcp", "TRQRCPResult", "trqrcp", "TUXVResult", "tuxv",

@@ -67,12 +67,6 @@ def unit_lower(qr, c=None):
     return y
 
 
-def upper(qr, rows=None):
-    """Upper-triangular/trapezoidal part R of an in-place QR array."""
-    rows = min(qr.shape) if rows is None else rows
-    return np.triu(np.asarray(qr[:rows, :], dtype=np.float64))
-
-
 def form_t(y, tau):
     """Compact-WY connection matrix T with H_1 ... H_c = I - Y T Y^T (Section 2.1).
 
@@ -86,15 +80,6 @@ def form_t(y, tau):
         if j:
             t[:j, j] = -tau[j] * (t[:j, :j] @ (y[:, :j].T @ y[:, j]))
     return t
-
-
-def apply_qt(y, tau, c_mat):
-    """Q^T C with Q = H_1 ... H_c applied one reflector at a time (no blocking)."""
-    out = np.array(c_mat, dtype=np.float64, copy=True)
-    for j in range(y.shape[1]):
-        v = y[:, j]
-        out -= tau[j] * np.outer(v, v @ out)
-    return out
 
 
 def form_q(y, tau, ncols=None):

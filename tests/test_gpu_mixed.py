@@ -68,7 +68,7 @@ def test_trqrcp_mixed_error_ratio(api, m, n, k, b, p, scale):
     api.default_handle(0).sync()
     jpvt, Y, T, R = (x.cpu().numpy() for x in (jpvt, Y, T, R))
     assert sorted(jpvt) == list(range(n))
-    np.testing.assert_allclose(Y.T @ Y - Y.T @ Y, 0.0)   # finite
+    assert np.isfinite(Y).all() and np.isfinite(T).all() and np.isfinite(R).all()
     q = np.eye(m) - Y @ T @ Y.T
     assert np.linalg.norm(q.T @ q - np.eye(m), 2) <= 1e-12
     ref = oracle.trqrcp(a32.astype(np.float64), om, b, p, k)

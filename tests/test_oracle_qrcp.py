@@ -144,8 +144,10 @@ def test_partial_qrcp_trailing_frobenius_equals_trailing_norms():
     a = synth.gaussian((30, 25), 41)
     r = np.array(a, copy=True)
     tau, piv = oracle.qrcp_inplace(r, 7)
-    nu = np.linalg.norm(r[7:, 7:], axis=0)
-    assert np.sum(nu ** 2) == pytest.approx(np.linalg.norm(r[7:, 7:], "fro") ** 2, rel=1e-14)
+    # orthogonal invariance: ||A||_F^2 = ||R(0:7, :)||_F^2 + ||trailing block||_F^2
+    top = np.triu(r[:7])
+    assert np.linalg.norm(a) ** 2 == pytest.approx(
+        np.linalg.norm(top) ** 2 + np.linalg.norm(r[7:, 7:]) ** 2, rel=1e-13)
     # and the leading 7 rows + trailing block reproduce A P up to the 7 reflections
     perm = np.arange(25)
     oracle.apply_transpositions(perm, piv, axis=0)
