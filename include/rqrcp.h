@@ -252,6 +252,26 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
                          int64_t ldb, int64_t* perm);
 
 /*
+ * rq_sample_qrcp_noalloc -- rq_sample_qrcp for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * rq_sample_qrcp, but the exchange records and column maps live in a static
+ * device array of the library (about 6.6 MB per device, held until the process
+ * ends) instead of the handle's workspace, and the call allocates nothing:
+ * no hipMalloc, hipFree or memset, only kernel launches on the handle's stream.
+ * Limit: n <= RQ_NOALLOC_MAX_N, else RQ_E_UNSUPPORTED before anything is
+ * enqueued.  Every call on one device shares that device's array, which keeps
+ * the last call's contents (each call re-marks what it uses), so calls that
+ * overlap in time on one device -- from two handles or two streams -- race and
+ * must be serialized by the caller.  RQ_E_HIP when the array's device address
+ * could not be looked up at rq_create.
+ * Argument numbers: h=1 ell=2 n=3 steps=4 B=5 ldb=6 perm=7.
+ */
+#define RQ_NOALLOC_MAX_N 16384
+rq_status rq_sample_qrcp_noalloc(rq_handle h, int64_t ell, int64_t n, int64_t steps, double* B,
+                                 int64_t ldb, int64_t* perm);
+
+/*
  * Kernel timing for measurement.  Between rq_profile_start and rq_profile_stop
  * every kernel the handle launches is bracketed by HIP events on the stream it
  * runs on and attributed to a named kernel class together with its algorithmic

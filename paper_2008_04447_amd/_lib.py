@@ -37,6 +37,7 @@ SIGNATURES = {
     "rq_sketch": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
                                    c_i64, c_p, c_i64]),
     "rq_sample_qrcp": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_p, c_i64, c_p]),
+    "rq_sample_qrcp_noalloc": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_p, c_i64, c_p]),
     "rq_profile_classes": (ctypes.c_int32, [c_p, ctypes.c_uint32]),
     "rq_profile_start": (ctypes.c_int32, [c_p]),
     "rq_profile_stop": (ctypes.c_int32, [c_p]),

@@ -223,6 +223,16 @@ def sample_qrcp(B, steps, handle=None):
     return perm
 
 
+def sample_qrcp_noalloc(B, steps, perm, handle=None):
+    """sample_qrcp without any device allocation: the library's static scratch
+    array holds the exchange records and ``perm`` (int64, n) is caller-provided."""
+    h = handle or default_handle(B.device.index)
+    ell, n = B.shape
+    rc = _lib.load().rq_sample_qrcp_noalloc(h.ptr, ell, n, steps, _ptr(B), ld(B), _ptr(perm))
+    _check("rq_sample_qrcp_noalloc", rc, h)
+    return perm
+
+
 # ----------------------------------------------------------------------------- serving
 def pinned_empty(shape, dtype):
     """Page-locked host array in column-major order (asynchronous copies)."""

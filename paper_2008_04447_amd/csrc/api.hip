@@ -272,6 +272,19 @@ rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R1
 
 using namespace rq;
 
+// Scratch memory of rq_sample_qrcp_noalloc, which allocates nothing: the
+// exchange records of one sample-QRCP launch of up to RQ_NOALLOC_MAX_N columns
+// (64 steps x 128 workgroups x a 100-word record) and the two column maps.
+// Each device holds its own copy until the process ends; calls that overlap on
+// one device share it and race.
+namespace {
+constexpr size_t kScratchRec = (size_t)RQ_MAX_B * 128 * (RQ_MAX_ELL + 4);
+constexpr size_t kScratchDoubles = kScratchRec + 2 * 64;
+static_assert(kScratchRec >= (size_t)RQ_MAX_B * ((RQ_NOALLOC_MAX_N + 127) / 128) * (RQ_MAX_ELL + 4),
+              "records of the widest sample fit");
+}  // namespace
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 extern "C" {
 
 rq_status rq_create(rq_handle* out, int device, void* hip_stream) {
@@ -293,6 +306,18 @@ rq_status rq_create(rq_handle* out, int device, void* hip_stream) {
   if (e == hipSuccess) e = hipMemsetAsync(h->status, 0, 4 * sizeof(int64_t), h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->sync, 0, 64 * sizeof(uint32_t), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) {
+    // the device address of this device's copy of the static scratch array
+    // (the array's name is only a host-side stand-in)
+    void* p = nullptr;
+    const hipError_t es = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (es == hipSuccess) {
+      h->scratch = static_cast<double*>(p);
+    } else {
+      h->last_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(es);
+      (void)hipGetLastError();
+    }
+  }
   if (e != hipSuccess) {
     if (h->status) (void)hipFree(h->status);
     if (h->sync) (void)hipFree(h->sync);
@@ -442,6 +467,45 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
   RQ_CHECK(h, launch_iota(perm, (int)n, h->stream));
   if (steps == 0) return RQ_OK;
   return run_sample_qrcp(h, B, ldb, (int)ell, n, (int)steps, w, perm);
+}
+
+rq_status rq_sample_qrcp_noalloc(rq_handle h, int64_t ell, int64_t n, int64_t steps, double* B,
+                                 int64_t ldb, int64_t* perm) {
+  if (!h) return -1;
+  if (ell < 1 || ell > RQ_MAX_ELL) return -2;
+  if (n < 0 || n > RQ_MAX_N) return -3;
+  if (steps < 0 || steps > std::min(ell, n) || steps > RQ_MAX_B) return -4;
+  if (!valid_ptr(B, ell * n)) return -5;
+  if (ldb < ell) return -6;
+  if (!valid_ptr(perm, n)) return -7;
+  if (n > RQ_NOALLOC_MAX_N) return RQ_E_UNSUPPORTED;   // beyond the static scratch
+  if (n == 0) return RQ_OK;
+  if (steps > 0 && !rows_fit(h, n)) return RQ_E_UNSUPPORTED;
+  if (!h->scratch) return RQ_E_HIP;     // the address lookup at rq_create failed
+  DeviceGuard guard(h->device);
+  SqArgs a{};
+  a.B = B;
+  a.ldb = ldb;
+  a.ell = (int)ell;
+  a.N = (int)n;
+  a.steps = (int)steps;
+  a.nwg = sq_groups(n, h->max_groups);
+  a.rs = sq_record_stride(sq_lm((int)ell));
+  a.rec = h->scratch;
+  a.counter = h->sync;
+  a.abort_flag = h->sync + 1;
+  a.status = h->status;
+  a.src_top = reinterpret_cast<int*>(h->scratch + kScratchRec);
+  a.dst_low = reinterpret_cast<int*>(h->scratch + kScratchRec + 64);
+  a.perm = perm;
+  const int64_t words = steps * (int64_t)a.nwg * a.rs;
+  if ((size_t)words > kScratchRec) return RQ_E_UNSUPPORTED;
+  RQ_CHECK(h, launch_iota(perm, (int)n, h->stream));
+  if (steps == 0) return RQ_OK;
+  // a fill kernel (not a memset) marks the records unpublished and clears the flags
+  RQ_CHECK(h, launch_exchange_prep(h->sync, h->scratch, words, h->stream));
+  RQ_CHECK(h, launch_sample_qrcp(a, sq_lm((int)ell), h->stream));
+  return RQ_OK;
 }
 
 }  // extern "C"

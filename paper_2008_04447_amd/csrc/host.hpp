@@ -66,6 +66,7 @@ struct rq_handle_s {
   int cus = 256;               // compute units of the device
   hipStream_t side = nullptr;  // second stream of the RQRCP block loop (created on first use)
   hipEvent_t ev_z = nullptr, ev_u = nullptr;
+  double* scratch = nullptr;   // device address of the static scratch array (rq_sample_qrcp_noalloc)
   std::string last_error;
   bool prof = false;
   uint32_t prof_mask = ~0u;     // kernel classes timed while prof is set

@@ -111,6 +111,17 @@ def test_tuxv_iter_jmax_is_argument_19(lib):
     assert lib.tuxv_svd_iter(FAKE, *args, 0) == -19
 
 
+def test_noalloc_argument_validation(lib):
+    buf = ctypes.c_void_p(0x2000)
+    assert lib.rq_sample_qrcp_noalloc(None, 8, 100, 4, buf, 8, buf) == -1
+    assert lib.rq_sample_qrcp_noalloc(FAKE, 97, 100, 4, buf, 97, buf) == -2
+    assert lib.rq_sample_qrcp_noalloc(FAKE, 8, 100, 9, buf, 8, buf) == -4
+    assert lib.rq_sample_qrcp_noalloc(FAKE, 8, 100, 4, buf, 7, buf) == -6
+    assert lib.rq_sample_qrcp_noalloc(FAKE, 8, 100, 4, buf, 8, None) == -7
+    # beyond the static scratch: refused before the handle is used
+    assert lib.rq_sample_qrcp_noalloc(FAKE, 8, 16385, 4, buf, 8, buf) == 1003
+
+
 def _declared_params():
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     out = {}
