@@ -12,6 +12,12 @@ here.
 
 Readings where the paper is silent:
 * the last block takes b_J = k - (J-1) b columns while ell stays b + p;
+* eq. (update1) needs R11 nonsingular (Section 3.2).  When a block's R11 has a
+  diagonal entry with |R_ii| <= eps max(m, n) |R_00| (numerically singular),
+  ``info`` records that column (1-based) and from then on every next sample is
+  a fresh projection of the updated trailing matrix (repeated sampling,
+  Section 3.4), B = Omega[:, :M'] A^[J], with the leading M' columns of the
+  given Omega (no new random matrix is drawn here);
 * R11^{-1} R12 is a triangular solve, then multiplied by S11;
 * the block transformation is applied as A <- A - Y (T^T (Y^T A)), i.e. Q^T A
   with Q = I - Y T Y^T built by the forward recurrence.
@@ -36,6 +42,7 @@ class RQRCPResult:
     trace: PivotTrace       # sample norms per step (best / runner-up)
     sample_scale: float     # largest initial sample column norm
     blocks: list = field(default_factory=list)   # optional per-block records
+    info: int = 0           # 0, or the 1-based column where R11 was numerically singular
 
 
 def _block_loop(a, k, b, first_sample, next_sample, keep_blocks=False):
@@ -99,15 +106,27 @@ def rqrcp(a, omega, b, p, k=None, keep_blocks=False):
     ell = b + p
     if np.shape(omega) != (ell, m):
         raise ValueError("omega must be (b+p) x m")
+    om = np.asarray(omega, dtype=np.float64)
+    eps = np.finfo(np.float64).eps
+    state = {"fallback": False, "info": 0}
 
     def first(w):
-        return np.asarray(omega, dtype=np.float64) @ w      # B^[0] = Omega A
+        return om @ w                                       # B^[0] = Omega A
 
     def nxt(sq, r11, r12, w, col0, bj):
+        # col0 is the next block's first column; w[0, 0] is R_00
+        if not state["fallback"]:
+            small = np.flatnonzero(np.abs(np.diag(r11)) <= eps * max(m, n) * abs(w[0, 0]))
+            if small.size:                                  # R11 numerically singular
+                state["fallback"] = True
+                state["info"] = col0 - bj + int(small[0]) + 1
+        if state["fallback"]:
+            trailing = w[col0:, col0:]                      # A^[J], already updated
+            return om[:, :trailing.shape[0]] @ trailing     # a fresh projection
         return sample_update(sq, r11, r12, bj)
 
     w, tau, jpvt, tb, trace, scale, blocks = _block_loop(a, k, b, first, nxt, keep_blocks)
-    return RQRCPResult(w, tau, jpvt, tb, trace, scale, blocks)
+    return RQRCPResult(w, tau, jpvt, tb, trace, scale, blocks, state["info"])
 
 
 def rsrqrcp(a, omegas, b, p, k=None):

@@ -191,3 +191,68 @@ def test_latent_cdf_matches_figure1_caption():
         freq = np.mean(phi < tau)
         sd = np.sqrt(exact * (1 - exact) / trials)
         assert abs(freq - exact) <= 5 * sd
+
+
+# ----------------------------------------------------------------------------- rank fallback
+def _zero_columns(m, n, r, seed):
+    """m x n with r Gaussian columns and n - r exactly zero columns at seeded positions."""
+    a = synth.gaussian((m, n), seed)
+    zero = synth.rng(seed + 1).permutation(n)[:n - r]
+    a[:, zero] = 0.0
+    return a, np.sort(zero)
+
+
+def test_rank_fallback_info_on_zero_columns():
+    """Eq. (update1) divides by R11 (Section 3.2).  With r nonzero columns, R_jj = 0
+    exactly from j = r on, so the block holding column r reports info = r + 1 and
+    the later samples are fresh projections: the result stays finite and is still a
+    valid pivoted QR, with an exactly zero trailing block."""
+    m, n, r, b, p = 120, 90, 50, 16, 8
+    a, zero = _zero_columns(m, n, r, 81)
+    res = oracle.rqrcp(a, synth.omega(b + p, m, 82), b, p)
+    assert res.info == r + 1
+    assert np.isfinite(res.qr).all() and np.isfinite(res.tau).all()
+    assert set(res.jpvt[r:]) == set(zero)
+    assert np.all(np.triu(res.qr)[r:] == 0.0)
+    q = q_from_inplace(res.qr, res.tau)
+    assert np.linalg.norm(a[:, res.jpvt] - q @ np.triu(res.qr)) <= 1e-13 * np.linalg.norm(a)
+    assert spectral_norm(q.T @ q - np.eye(m)) <= 1e-13
+    # the same matrix through plain eq. (update1) would divide by zero
+    with np.errstate(all="ignore"):
+        blk = oracle.rqrcp(a, synth.omega(b + p, m, 82), b, p, k=64, keep_blocks=True).blocks[3]
+    assert np.min(np.abs(np.diag(blk["r11"]))) == 0.0
+
+
+def test_rank_fallback_identity_compression_reduces_to_qrcp():
+    """With Omega = I (ell = m) every sample, updated or re-projected, carries the
+    exact trailing norms, so RQRCP with the fallback picks QRCP's pivots at every
+    step, past the rank too (zero columns tie and go by position on both sides).
+    A fallback that projected the matrix before its block update, or the wrong
+    rows of it, would change the pivots after the fallback."""
+    m, n, b, p = 48, 40, 8, 40
+    a, _ = synth.graded_known_pivots(m, n, 83, ratio=0.8)
+    a[:, synth.rng(84).permutation(n)[:12]] = 0.0
+    res = oracle.rqrcp(a, np.eye(m), b, p)
+    ref = oracle.qrcp(a)
+    assert res.info == 29
+    np.testing.assert_array_equal(res.jpvt, ref.jpvt)
+    np.testing.assert_allclose(np.abs(np.triu(res.qr)[:n]), np.abs(np.triu(ref.qr)[:n]),
+                               rtol=1e-10, atol=1e-13)
+
+
+def test_rank_fallback_quiet_on_full_rank():
+    m, n, b, p = 300, 240, 32, 8
+    sig = synth.spectrum("pow10", 240, scale=40.0)
+    a = synth.low_rank(m, n, sig, 85, 86)
+    assert oracle.rqrcp(a, synth.omega(b + p, m, 87), b, p).info == 0
+
+
+def test_exact_tie_goes_to_lowest_position():
+    """Duplicated columns give bitwise-equal sample norms: the first step is an
+    exact tie, which the lowest current position wins (reading c2)."""
+    a = synth.gaussian((300, 240), 11)
+    a[:, 3] *= 10.0
+    a[:, 7] = a[:, 3]
+    res = oracle.rqrcp(a, synth.omega(40, 300, 12), 32, 8)
+    assert res.trace.best[0] == res.trace.second[0]
+    assert res.jpvt[0] == 3
