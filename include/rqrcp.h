@@ -65,6 +65,17 @@ typedef enum {
 
 typedef struct rq_handle_s* rq_handle;
 
+/* Operations, for rq_workspace_query and the serving loop's requests. */
+enum {
+  RQ_OP_TRQRCP = 0,      /* trqrcp_truncate                                    */
+  RQ_OP_TUXV = 1,        /* tuxv_svd / tuxv_svd_iter                           */
+  RQ_OP_RQRCP = 2,       /* rqrcp_factor                                       */
+  RQ_OP_RSRQRCP = 3,     /* rsrqrcp_factor                                     */
+  RQ_OP_QRCP = 4,        /* qrcp_factor (b = nb, p ignored)                    */
+  RQ_OP_SKETCH = 5,      /* rq_sketch (b + p = ell, k ignored)                 */
+  RQ_OP_SAMPLE_QRCP = 6  /* rq_sample_qrcp (b + p = ell, k = steps, m ignored) */
+};
+
 /* Library limits (checked by every entry point):
  * 1 <= b <= 64, p >= 0, b + p <= 96, n <= 65536.  The persistent kernels put
  * one workgroup of 256 rows (or sample columns) on each compute unit, all
@@ -96,6 +107,25 @@ rq_status rq_sync_status(rq_handle h, int64_t* device_error);
 const char* rq_last_error(rq_handle h);
 
 /*
+ * Workspace.  Each entry point carves its scratch (samples, split-K partials,
+ * exchange records, reflector buffers) out of one device buffer owned by the
+ * handle, which grows with hipMalloc when a call needs more and is never
+ * shrunk.  rq_workspace_query reports, without touching the device, the bytes
+ * the call `op` (RQ_OP_*) would need for the given sizes, so a caller can
+ * budget HBM or grow the buffer ahead of time with rq_workspace_reserve (for
+ * example before a timed or captured region, after which no call of at most
+ * those sizes allocates); rq_workspace_size reports the current size.  The
+ * sizes mean what they mean for the entry point named by op; see the RQ_OP_*
+ * list for the ones an op ignores.
+ * Errors of the query: -1 h, -2 op, -3 prec, -4 m, -5 n, -6 k, -7 b, -8 p,
+ * -9 bytes == NULL; reserve returns RQ_E_NOMEM when the allocation fails.
+ */
+rq_status rq_workspace_query(rq_handle h, int32_t op, rq_prec prec, int64_t m, int64_t n, int64_t k,
+                             int64_t b, int64_t p, size_t* bytes);
+rq_status rq_workspace_reserve(rq_handle h, size_t bytes);
+rq_status rq_workspace_size(rq_handle h, size_t* bytes);
+
+/*
  * rqrcp_factor -- RQRCP, Algorithm 4 (Section 3.4), with the sample update
  * formula eq. (update1): B1 = S12 - S11 R11^{-1} R12, B2 = S22.
  *
@@ -116,16 +146,24 @@ const char* rq_last_error(rq_handle h);
  *  T, ldt    out: b x k block-T (like dgeqrt): for the block starting at column
  *            c0 with width bJ, T[0:bJ, c0:c0+bJ] is upper triangular with
  *            H_c0 ... H_{c0+bJ-1} = I - Y_J T_J Y_J^T.  ldt >= b.  May be NULL.
- * The sample update divides by R11: an exactly singular R11 (say a block of
- * all-zero columns) makes the updated sample non-finite, which is reported as
- * RQ_DEV_NONFINITE / RQ_DEV_NO_PIVOT and leaves the later blocks unpivoted;
- * rsrqrcp_factor needs no R11^{-1}.
+ *  info      out: device int64 (may be NULL).  eq. (update1) needs R11
+ *            nonsingular (Section 3.2).  After each block's panel every
+ *            diagonal entry of its R11 is tested against eps max(m, n) |R_00|
+ *            (eps = 2^-52, R_00 the first diagonal entry of R); the first time
+ *            one is not larger, *info receives its 1-based column index and
+ *            from then on each next sample is a fresh projection of the updated
+ *            trailing matrix, B = Omega(:, 0:m-c) A^[J] with Omega's leading
+ *            m - c columns (c = the next block's first column: repeated
+ *            sampling, Section 3.4, with the given Omega) instead of the sample
+ *            update.  *info = 0 when the sample update was used throughout.
+ *            A rank-deficient A thus factors with finite R and a valid
+ *            permutation; it is a numerical warning, not an error.
  * Argument numbers for errors: h=1 m=2 n=3 k=4 b=5 p=6 A=7 lda=8 Omega=9
- * ldo=10 jpvt=11 tau=12 T=13 ldt=14.
+ * ldo=10 jpvt=11 tau=12 T=13 ldt=14 info=15.
  */
 rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
                        double* A, int64_t lda, const double* Omega, int64_t ldo,
-                       int64_t* jpvt, double* tau, double* T, int64_t ldt);
+                       int64_t* jpvt, double* tau, double* T, int64_t ldt, int64_t* info);
 
 /*
  * rsrqrcp_factor -- RQRCP with repeated sampling (Section 3.4): Algorithm 4
@@ -321,7 +359,6 @@ rq_status rq_profile_get(rq_handle h, int32_t index, const char** name, int64_t*
  */
 typedef struct rq_server_s* rq_server;
 
-enum { RQ_OP_TRQRCP = 0, RQ_OP_TUXV = 1 };
 enum { RQ_REQ_QUEUED = 0, RQ_REQ_RUNNING = 1, RQ_REQ_DONE = 2, RQ_REQ_FAILED = 3 };
 
 typedef struct {

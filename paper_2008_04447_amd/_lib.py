@@ -21,8 +21,12 @@ SIGNATURES = {
     "rq_set_stream": (ctypes.c_int32, [c_p, c_p]),
     "rq_sync_status": (ctypes.c_int32, [c_p, ctypes.POINTER(c_i64)]),
     "rq_last_error": (ctypes.c_char_p, [c_p]),
+    "rq_workspace_query": (ctypes.c_int32, [c_p, ctypes.c_int32, ctypes.c_int, c_i64, c_i64, c_i64,
+                                            c_i64, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "rq_workspace_reserve": (ctypes.c_int32, [c_p, ctypes.c_size_t]),
+    "rq_workspace_size": (ctypes.c_int32, [c_p, ctypes.POINTER(ctypes.c_size_t)]),
     "rqrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
-                                      c_i64, c_p, c_p, c_p, c_i64]),
+                                      c_i64, c_p, c_p, c_p, c_i64, c_p]),
     "rsrqrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
                                         c_i64, c_i64, c_p, c_p, c_p, c_i64]),
     "qrcp_factor": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_i64, c_p, c_i64, c_p, c_p]),
@@ -73,6 +77,11 @@ class Result(ctypes.Structure):
 
 RQ_OP_TRQRCP = 0
 RQ_OP_TUXV = 1
+RQ_OP_RQRCP = 2
+RQ_OP_RSRQRCP = 3
+RQ_OP_QRCP = 4
+RQ_OP_SKETCH = 5
+RQ_OP_SAMPLE_QRCP = 6
 RQ_REQ_DONE = 2
 RQ_REQ_FAILED = 3
 

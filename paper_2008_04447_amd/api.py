@@ -75,6 +75,21 @@ class Handle:
             raise RQError("rq_sync_status", rc, f"device_error bits = {err.value}")
         return 0
 
+    def workspace_query(self, op, m, n, k, b, p, prec=RQ_FP64):
+        """Workspace bytes the entry point ``op`` (an RQ_OP_* code) needs."""
+        out = ctypes.c_size_t(0)
+        _check("rq_workspace_query", _lib.load().rq_workspace_query(
+            self.ptr, int(op), int(prec), m, n, k, b, p, ctypes.byref(out)))
+        return out.value
+
+    def workspace_reserve(self, nbytes):
+        _check("rq_workspace_reserve", _lib.load().rq_workspace_reserve(self.ptr, int(nbytes)), self)
+
+    def workspace_size(self):
+        out = ctypes.c_size_t(0)
+        _check("rq_workspace_size", _lib.load().rq_workspace_size(self.ptr, ctypes.byref(out)))
+        return out.value
+
     def close(self):
         if self.ptr:
             _lib.load().rq_destroy(self.ptr)
@@ -105,7 +120,9 @@ def default_handle(device=None):
 def rqrcp_factor(A, Omega, b, p, k=None, handle=None):
     """RQRCP (Algorithm 4) in place on the column-major float64 tensor A.
 
-    Returns (jpvt, tau, T) as device tensors; A holds R and the reflectors.
+    Returns (jpvt, tau, T, info) as device tensors; A holds R and the
+    reflectors, info (one int64) is 0 or the 1-based column at which R11 was
+    numerically singular and fresh samples replaced the sample update.
     """
     h = handle or default_handle(A.device.index)
     m, n = A.shape
@@ -114,10 +131,11 @@ def rqrcp_factor(A, Omega, b, p, k=None, handle=None):
     jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
     tau = torch.empty(max(k, 1), dtype=torch.float64, device=dev)[:k]
     T = empty_colmajor(b, max(k, 1), torch.float64, dev)
+    info = torch.zeros(1, dtype=torch.int64, device=dev)
     rc = _lib.load().rqrcp_factor(h.ptr, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
-                                  ld(Omega), _ptr(jpvt), _ptr(tau), _ptr(T), ld(T))
+                                  ld(Omega), _ptr(jpvt), _ptr(tau), _ptr(T), ld(T), _ptr(info))
     _check("rqrcp_factor", rc, h)
-    return jpvt, tau, T
+    return jpvt, tau, T, info
 
 
 def rsrqrcp_factor(A, Omegas, b, p, k=None, handle=None):

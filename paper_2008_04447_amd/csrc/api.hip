@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cstring>
 #include <string>
 
@@ -241,10 +242,11 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
 // B1 = S12 - (S11 R11^{-1}) R12 in place on rows 0..bj-1 of the sample block
 // (columns bj..), B2 = S22 untouched (eq. update1).
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
-                            const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat) {
+                            const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat,
+                            const RankCheck* rk) {
   {
     KTimer kt(h, K_OMEGA11, (double)bj * bj * bj / 3.0, 8.0 * 2 * bj * bj);
-    RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, h->stream));
+    RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, rk, h->stream));
   }
   GemmArgs u{};
   u.L = mhat;
@@ -263,6 +265,7 @@ rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R1
   u.beta = 1.0;
   u.C = sblk + (int64_t)bj * ell;
   u.ldc = ell;
+  u.skip_if = rk ? rk->info : nullptr;
   KTimer kt(h, K_SAMPLE_UPDATE, 2.0 * bj * bj * (double)Nt, 8.0 * 3.0 * bj * (double)Nt);
   RQ_CHECK(h, launch_gemm_lx(u, h->stream));
   return RQ_OK;
@@ -365,6 +368,56 @@ rq_status rq_sync_status(rq_handle h, int64_t* device_error) {
   return st[0] ? RQ_E_DEVICE : RQ_OK;
 }
 
+rq_status rq_workspace_query(rq_handle h, int32_t op, rq_prec prec, int64_t m, int64_t n, int64_t k,
+                             int64_t b, int64_t p, size_t* bytes) {
+  if (!h) return -1;
+  if (op < RQ_OP_TRQRCP || op > RQ_OP_SAMPLE_QRCP) return -2;
+  if (prec != RQ_FP64 && prec != RQ_MIXED_BF16) return -3;
+  if (m < 0) return -4;
+  if (n < 0 || n > RQ_MAX_N) return -5;
+  if (!bytes) return -9;
+  const int64_t ell = b + p;
+  switch (op) {
+    case RQ_OP_QRCP:
+      if (k < 0 || k > std::min(m, n)) return -6;
+      if (b < 1 || b > 64) return -7;
+      *bytes = qrcp_workspace_bytes(m, n, k);
+      return RQ_OK;
+    case RQ_OP_SKETCH:
+      if (ell < 1 || ell > RQ_MAX_ELL) return -7;
+      *bytes = sketch_workspace_bytes(ell, m, n);
+      return RQ_OK;
+    case RQ_OP_SAMPLE_QRCP:
+      if (ell < 1 || ell > RQ_MAX_ELL) return -7;
+      if (k < 0 || k > std::min(ell, n) || k > RQ_MAX_B) return -6;
+      *bytes = (k > 0) ? sample_qrcp_workspace_bytes(ell, n) : 0;
+      return RQ_OK;
+    default:
+      break;
+  }
+  if (k < 0 || k > std::min(m, n)) return -6;
+  if (b < 1 || b > RQ_MAX_B) return -7;
+  if (p < 0 || ell > RQ_MAX_ELL || (k > 0 && ell > m)) return -8;
+  if (op == RQ_OP_RQRCP || op == RQ_OP_RSRQRCP)
+    *bytes = rqrcp_workspace_bytes(m, n, k, b, p, op == RQ_OP_RSRQRCP);
+  else
+    *bytes = (k > 0 && n > 0) ? truncated_workspace_bytes(m, n, k, (int)ell, op == RQ_OP_TUXV) : 0;
+  return RQ_OK;
+}
+
+rq_status rq_workspace_reserve(rq_handle h, size_t bytes) {
+  if (!h) return -1;
+  DeviceGuard guard(h->device);
+  return reserve(h, bytes);
+}
+
+rq_status rq_workspace_size(rq_handle h, size_t* bytes) {
+  if (!h) return -1;
+  if (!bytes) return -2;
+  *bytes = h->ws_bytes;
+  return RQ_OK;
+}
+
 rq_status rq_profile_classes(rq_handle h, uint32_t mask) {
   if (!h) return -1;
   h->prof_mask = mask;
@@ -434,7 +487,7 @@ rq_status rq_sketch(rq_handle h, rq_prec prec, int64_t ell, int64_t m, int64_t n
   const size_t np = std::max(sketch_part_doubles((int)ell, m, n),
                              sketch_part_doubles_bf16((int)ell, m, n));
   const size_t nl = bf16_stage_doubles(m);
-  RQ_TRY(reserve(h, padded_bytes(np) + padded_bytes(nl)));
+  RQ_TRY(reserve(h, sketch_workspace_bytes(ell, m, n)));
   Carve cv(h->ws);
   double* part = cv.take<double>(np);
   __bf16* lbf = reinterpret_cast<__bf16*>(cv.take<double>(nl));
@@ -457,7 +510,7 @@ rq_status rq_sample_qrcp(rq_handle h, int64_t ell, int64_t n, int64_t steps, dou
   if (n == 0) return RQ_OK;
   if (steps > 0 && !rows_fit(h, n)) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
-  RQ_TRY(reserve(h, padded_bytes(sq_rec_doubles((int)ell, n)) + 2 * 64 * sizeof(int) + 512));
+  RQ_TRY(reserve(h, sample_qrcp_workspace_bytes(ell, n)));
   Carve cv(h->ws);
   SqWork w;
   w.rec = cv.take<double>(sq_rec_doubles((int)ell, n));
@@ -510,6 +563,45 @@ rq_status rq_sample_qrcp_noalloc(rq_handle h, int64_t ell, int64_t n, int64_t st
 
 }  // extern "C"
 
+// Largest split-K buffer of any block of the RQRCP loop (and of the sketches).
+static size_t rqrcp_part_doubles(int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
+                                 bool resample) {
+  const int64_t ell = b + p;
+  size_t w_part = 0;
+  for (int64_t c0 = 0; c0 < k; c0 += b) {
+    const int64_t nt = n - c0 - std::min<int64_t>(b, k - c0);
+    if (nt <= 0) continue;
+    int ks_b, kc_b;
+    plan_split((int)(m - c0), (int)nt, &ks_b, &kc_b);
+    w_part = std::max(w_part, (size_t)ks_b * 64 * nt);
+    const int64_t c1 = c0 + std::min<int64_t>(b, k - c0);     // next block's sketch
+    if (resample && c1 < k) w_part = std::max(w_part, sketch_part_doubles((int)ell, m - c1, n - c1));
+  }
+  return std::max(w_part, sketch_part_doubles((int)ell, m, n));
+}
+
+namespace rq {
+size_t rqrcp_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t b, int64_t p, bool resample) {
+  if (k <= 0 || n <= 0) return 0;
+  const int64_t ell = b + p;
+  return padded_bytes((size_t)ell * n) + padded_bytes(rqrcp_part_doubles(m, n, k, b, p, resample)) +
+         padded_bytes(sq_rec_doubles((int)ell, n)) + padded_bytes(panel_rec_doubles(m)) +
+         padded_bytes((size_t)m * 64) + 2 * padded_bytes(64 * 64) + padded_bytes((size_t)64 * n) +
+         4 * 64 * sizeof(int) + 1024;
+}
+
+size_t sketch_workspace_bytes(int64_t ell, int64_t m, int64_t n) {
+  if (n <= 0) return 0;
+  const size_t np = std::max(sketch_part_doubles((int)ell, m, n), sketch_part_doubles_bf16((int)ell, m, n));
+  return padded_bytes(np) + padded_bytes(bf16_stage_doubles(m));
+}
+
+size_t sample_qrcp_workspace_bytes(int64_t ell, int64_t n) {
+  if (n <= 0) return 0;
+  return padded_bytes(sq_rec_doubles((int)ell, n)) + 2 * 64 * sizeof(int) + 512;
+}
+}  // namespace rq
+
 // The block loop of Algorithm 4.  With `resample` (repeated sampling, Section
 // 3.4) the sample of block J is a fresh sketch of the updated trailing matrix,
 // B = Omega^[J] A^[J], with Omega^[J] the first m - Jb columns of the ell x m
@@ -517,7 +609,7 @@ rq_status rq_sample_qrcp_noalloc(rq_handle h, int64_t ell, int64_t n, int64_t st
 static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
                             double* A, int64_t lda, const double* Omega, int64_t ldo,
                             int64_t ostride, bool resample, int64_t* jpvt, double* tau, double* T,
-                            int64_t ldt) {
+                            int64_t ldt, int64_t* info) {
   if (!h) return -1;
   if (m < 0) return -2;
   if (n < 0 || n > RQ_MAX_N) return -3;
@@ -538,30 +630,25 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
   if (k > 0 && !rows_fit(h, std::max(m, n))) return RQ_E_UNSUPPORTED;
   DeviceGuard guard(h->device);
   hipStream_t s = h->stream;
-  if (k == 0) {
-    RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
-    return RQ_OK;
+  // the rank check's record: the caller's, else a spare word of the status area
+  int64_t* info_p = info ? info : h->status + 2;
+  if (k == 0 || resample) {
+    if (info) RQ_CHECK(h, launch_set_i64(info, 0, s));
+    if (k == 0) {
+      RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
+      return RQ_OK;
+    }
+  } else {
+    RQ_CHECK(h, launch_set_i64(info_p, 0, s));
   }
 
   // ---- workspace -------------------------------------------------------------
-  size_t w_part = 0;                                 // largest split-K buffer of any block
-  for (int64_t c0 = 0; c0 < k; c0 += b) {
-    const int64_t nt = n - c0 - std::min<int64_t>(b, k - c0);
-    if (nt <= 0) continue;
-    int ks_b, kc_b;
-    plan_split((int)(m - c0), (int)nt, &ks_b, &kc_b);
-    w_part = std::max(w_part, (size_t)ks_b * 64 * nt);
-    const int64_t c1 = c0 + std::min<int64_t>(b, k - c0);     // next block's sketch
-    if (resample && c1 < k) w_part = std::max(w_part, sketch_part_doubles((int)ell, m - c1, n - c1));
-  }
+  const size_t need = rqrcp_workspace_bytes(m, n, k, b, p, resample);
   const size_t n_sample = (size_t)ell * n;
-  const size_t n_part = std::max(w_part, sketch_part_doubles((int)ell, m, n));
+  const size_t n_part = rqrcp_part_doubles(m, n, k, b, p, resample);
   const size_t n_sqrec = sq_rec_doubles((int)ell, n);
   const size_t n_prec = panel_rec_doubles(m);
   const size_t n_y = (size_t)m * 64;
-  const size_t need = padded_bytes(n_sample) + padded_bytes(n_part) + padded_bytes(n_sqrec) +
-                      padded_bytes(n_prec) + padded_bytes(n_y) + 2 * padded_bytes(64 * 64) +
-                      padded_bytes((size_t)64 * n) + 4 * 64 * sizeof(int) + 1024;
   RQ_TRY(reserve(h, need));
   Carve cv(h->ws);
   double* sample = cv.take<double>(n_sample);
@@ -693,9 +780,31 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     // the next sample QRCP (see release_side); the next block waits for them
     // before it permutes and factors its panel.
     // 6. sample update B1 = S12 - S11 R11^{-1} R12, B2 = S22 (in place)
-    if (col0 + bj < k)
+    // (or, once R11 has been numerically singular, a fresh sample of the updated
+    // trailing matrix with Omega's first M - bj columns; see launch_omega11)
+    if (col0 + bj < k) {
+      RankCheck rk{};
+      rk.info = info_p;
+      rk.r00 = A;                     // R_00, the first diagonal entry of R
+      rk.thresh = DBL_EPSILON * (double)std::max(m, n);
+      rk.col0 = col0;
+      rk.Om = Omega;
+      rk.ldo = ldo;
+      rk.C = Ctr + bj;                // rows below R12, before their update
+      rk.ldc = lda;
+      rk.M2 = (int)(M - bj);
+      rk.Y = ybuf + bj;
+      rk.ldy = m;
+      rk.Z = zbuf;
+      rk.ldz = 64;
+      rk.bj = bj;
+      rk.ell = (int)ell;
+      rk.N = (int)Nt;
+      rk.B = sample + (col0 + bj) * ell;
+      rk.ldb = ell;
       RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
-                               mhat));
+                               mhat, &rk));
+    }
     if (M > bj) {
       side = SideUpdate{Ctr + bj, M - bj, Nt, ybuf + bj, bj};
       side_queued = true;
@@ -713,15 +822,16 @@ extern "C" {
 
 rq_status rqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
                        double* A, int64_t lda, const double* Omega, int64_t ldo, int64_t* jpvt,
-                       double* tau, double* T, int64_t ldt) {
-  return rqrcp_core(h, m, n, k, b, p, A, lda, Omega, ldo, 0, false, jpvt, tau, T, ldt);
+                       double* tau, double* T, int64_t ldt, int64_t* info) {
+  return rqrcp_core(h, m, n, k, b, p, A, lda, Omega, ldo, 0, false, jpvt, tau, T, ldt, info);
 }
 
 rq_status rsrqrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
                          double* A, int64_t lda, const double* Omegas, int64_t ldo,
                          int64_t ostride, int64_t* jpvt, double* tau, double* T, int64_t ldt) {
   if (h && k > 0 && b >= 1 && ldo >= b + p && m > 0 && ostride < ldo * m) return -11;
-  rq_status r = rqrcp_core(h, m, n, k, b, p, A, lda, Omegas, ldo, ostride, true, jpvt, tau, T, ldt);
+  rq_status r =
+      rqrcp_core(h, m, n, k, b, p, A, lda, Omegas, ldo, ostride, true, jpvt, tau, T, ldt, nullptr);
   if (r <= -11 && r >= -14) r -= 1;   // jpvt, tau, T, ldt come after ostride here
   return r;
 }

@@ -19,6 +19,8 @@ namespace rq {
 // 16 k values (both operands use the same ordering of k).
 template <int PB>
 __global__ __launch_bounds__(256) void gemm_lx_narrow_kernel(GemmArgs g) {
+  if (g.skip_if && __hip_atomic_load(g.skip_if, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+    return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + wave * 16 + (lane & 15);
@@ -383,6 +385,7 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
   if (g.kchunk <= 0 || g.kchunk % 16 != 0) return hipErrorInvalidValue;
   const int pb = (g.P + 15) / 16;
   const bool lk1 = g.sLk == 1;
+  if (g.skip_if && g.kchunk > 64) return hipErrorInvalidValue;   // only the narrow route skips
   if (lk1 && pb <= 4 && g.kchunk > 64) {
     dim3 grid((g.N + 31) / 32, g.ksplit);
     switch (pb) {
@@ -907,17 +910,110 @@ hipError_t launch_update(double* C, int64_t ldc, int M, int N, const double* Y, 
 }
 
 // ---------------------------------------------------------------------------
+// Fresh sample of the updated trailing matrix for one tile of kFreshCols
+// columns (64 threads): B(:, c) = Omega(:, 0:M2) (C(:, c) - Y Z(:, c)).
+RQ_DEV void fresh_sample_tile(const RankCheck& rk, int tile) {
+  __shared__ double s_z[64][kFreshCols];
+  __shared__ double s_u[kFreshRows][kFreshCols + 1];
+  __shared__ double s_om[kFreshRows][kFreshMaxEll + 1];
+  const int t = threadIdx.x;
+  const int c0 = tile * kFreshCols;
+#pragma unroll
+  for (int q = 0; q < kFreshCols; ++q) {
+    const int c = c0 + q;
+    s_z[t][q] = (t < rk.bj && c < rk.N) ? rk.Z[t + (int64_t)c * rk.ldz] : 0.0;
+  }
+  const int cc = t & (kFreshCols - 1), rg = t / kFreshCols;   // accumulation: column, row phase
+  const int rr = t & (kFreshRows - 1), hf = t / kFreshRows;   // staging: chunk row, half
+  constexpr int kAcc = kFreshMaxEll / 4;
+  double acc[kAcc];
+#pragma unroll
+  for (int q = 0; q < kAcc; ++q) acc[q] = 0.0;
+  for (int r0 = 0; r0 < rk.M2; r0 += kFreshRows) {
+    __syncthreads();   // s_z is staged and the previous chunk consumed
+    const int r = r0 + rr;
+    const bool rok = r < rk.M2;
+    double u[kFreshCols / 2];
+#pragma unroll
+    for (int q = 0; q < kFreshCols / 2; ++q) {
+      const int c = c0 + hf * (kFreshCols / 2) + q;
+      u[q] = (rok && c < rk.N) ? rk.C[r + (int64_t)c * rk.ldc] : 0.0;
+    }
+    for (int j = 0; j < rk.bj; ++j) {
+      const double y = rok ? rk.Y[r + (int64_t)j * rk.ldy] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kFreshCols / 2; ++q) u[q] = fma(-y, s_z[j][hf * (kFreshCols / 2) + q], u[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kFreshCols / 2; ++q) s_u[rr][hf * (kFreshCols / 2) + q] = u[q];
+#pragma unroll
+    for (int q = 0; q < kFreshMaxEll / 2; ++q) {
+      const int e = hf + 2 * q;
+      if (e < rk.ell) s_om[rr][e] = rok ? rk.Om[e + (int64_t)r * rk.ldo] : 0.0;
+    }
+    __syncthreads();
+    for (int x = 0; x < kFreshRows; ++x) {
+      const double uv = s_u[x][cc];
+#pragma unroll
+      for (int q = 0; q < kAcc; ++q) acc[q] = fma(s_om[x][rg + 4 * q], uv, acc[q]);
+    }
+  }
+  const int c = c0 + cc;
+  if (c < rk.N) {
+#pragma unroll
+    for (int q = 0; q < kAcc; ++q) {
+      const int e = rg + 4 * q;
+      if (e < rk.ell) rk.B[e + (int64_t)c * rk.ldb] = acc[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // omega11: Mhat = S11 R11^{-1} (both bj x bj upper triangular, so Mhat is too),
 // M[i + c ldm] = Mhat(i, c).  One single-wave workgroup per row
 // i (rows on different compute units); lane c holds column c of R11 in
 // registers and the reciprocal of R11(c, c).  Step c: m_c = s_c / R(c, c), then
 // s_c' -= m_c R(c, c') for c' > c, with s_c and 1 / R(c, c) read from lane c by
 // v_readlane.
+//
+// With a rank check (rk.info set), eq. (update1) is used only while R11 is
+// numerically nonsingular (Section 3.2 needs R11^{-1}): every workgroup tests
+// |R11(c, c)| <= rk.thresh |R_00| itself, so all take the same decision without
+// waiting for each other.  The first time the test fires, workgroup 0 records
+// the 1-based column in *rk.info; from then on (*rk.info != 0) the rows of
+// Mhat are not formed, the sample update product that follows skips itself,
+// and the extra workgroups bj.. of the launch write a fresh sample of the
+// updated trailing matrix instead (repeated sampling, Section 3.4):
+//   B = Omega(:, 0:M2) (C - Y Z),  C = the M2 x N rows below R12 before their
+// update, Y (M2 x bj) and Z = T^T W (bj x N) the block's reflection, so
+// C - Y Z is the trailing matrix A^[J] the next block factors.  Each extra
+// workgroup owns 16 columns of B: per chunk of 64 rows, thread t forms row t
+// of C - Y Z for those columns into LDS and stages column t of the Omega chunk,
+// then each thread accumulates ell / 4 rows of its column of B.
 __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t lds,
                                                      const double* R11, int64_t ldr, int bj,
-                                                     double* M, int64_t ldm) {
+                                                     double* M, int64_t ldm, RankCheck rk) {
   const int lane = threadIdx.x;
   const int i = blockIdx.x;
+  if (rk.info) {
+    bool resample = __hip_atomic_load(rk.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (!resample) {
+      const double lim = rk.thresh * fabs(*rk.r00);
+      const bool small = lane < bj && fabs(R11[lane + (int64_t)lane * ldr]) <= lim;
+      const unsigned long long hit = __builtin_amdgcn_ballot_w64(small);
+      if (hit) {
+        resample = true;
+        if (i == 0 && lane == 0)
+          __hip_atomic_store(rk.info, rk.col0 + (int64_t)__builtin_ctzll(hit) + 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (i >= bj) {
+      if (resample) fresh_sample_tile(rk, i - bj);
+      return;
+    }
+    if (resample) return;
+  }
   double rc[64];
 #pragma unroll
   for (int q = 0; q < 64; ++q)
@@ -937,9 +1033,18 @@ __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t 
 }
 
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr, int bj,
-                          double* M, int64_t ldm, hipStream_t s) {
+                          double* M, int64_t ldm, const RankCheck* rk, hipStream_t s) {
   if (bj < 1 || bj > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(omega11_kernel, dim3(bj), dim3(64), 0, s, S11, lds, R11, ldr, bj, M, ldm);
+  RankCheck r{};
+  int extra = 0;
+  if (rk) {
+    r = *rk;
+    if (!r.info || !r.r00 || r.ell < 1 || r.ell > kFreshMaxEll || r.N < 0 || r.M2 < 0)
+      return hipErrorInvalidValue;
+    extra = (r.N + kFreshCols - 1) / kFreshCols;
+  }
+  hipLaunchKernelGGL(omega11_kernel, dim3(bj + extra), dim3(64), 0, s, S11, lds, R11, ldr, bj, M,
+                     ldm, r);
   return hipGetLastError();
 }
 
@@ -1023,6 +1128,14 @@ __global__ void iota_kernel(int64_t* v, int n) {
 hipError_t launch_iota(int64_t* v, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 

@@ -176,9 +176,17 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt,
                     bool prepared = false);
+// With rk (RQRCP), the rank check of launch_omega11 runs in the same launch
+// and the product skips itself once rk->info is set.
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
-                            const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat);
-// Workspace bytes trqrcp_truncate / tuxv_svd reserve for a problem shape.
+                            const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat,
+                            const RankCheck* rk = nullptr);
+// Workspace bytes each entry point reserves for a problem shape (what
+// rq_workspace_query reports).
 size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv);
+size_t rqrcp_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t b, int64_t p, bool resample);
+size_t qrcp_workspace_bytes(int64_t m, int64_t n, int64_t k);
+size_t sketch_workspace_bytes(int64_t ell, int64_t m, int64_t n);
+size_t sample_qrcp_workspace_bytes(int64_t ell, int64_t n);
 
 }  // namespace rq

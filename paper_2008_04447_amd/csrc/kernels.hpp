@@ -59,6 +59,7 @@ struct GemmArgs {
   double alpha, beta;                  // ksplit == 1: out = alpha * LX + beta * C
   const double* C; int64_t ldc;
   const int64_t* xcol = nullptr;       // optional: column n of X is X + xcol[n] * ldx
+  const int64_t* skip_if = nullptr;    // optional (K <= 64 only): no work when *skip_if != 0
 };
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
 // split-K plan of launch_gemm_lx for P output rows (kchunk a multiple of 64)
@@ -141,9 +142,28 @@ hipError_t launch_tcompose(double* T, int64_t ldt, int c0, int bj, const double*
 hipError_t launch_scatter_t(const double* R, int64_t ldr, int k, int n, const int64_t* col,
                             double* Z0T, int64_t ldz, hipStream_t s);
 
-// Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr.
+// Rank check of the sample update and the fresh sample that replaces it once
+// R11 is numerically singular (|R11(c, c)| <= thresh |R_00|): *info (zero at
+// the start of the factorization) receives col0 + c + 1 the first time, and
+// from then on B (ell x N, ld ldb) = Omega(:, 0:M2) (C - Y Z) with C M2 x N,
+// Y M2 x bj, Z bj x N.
+constexpr int kFreshCols = 16;    // columns of B per workgroup
+constexpr int kFreshRows = 32;    // rows of C per LDS chunk
+constexpr int kFreshMaxEll = 96;
+struct RankCheck {
+  int64_t* info; const double* r00; double thresh; int64_t col0;
+  const double* Om; int64_t ldo;
+  const double* C; int64_t ldc; int M2;
+  const double* Y; int64_t ldy;
+  const double* Z; int64_t ldz;
+  int bj, ell, N;
+  double* B; int64_t ldb;
+};
+// Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr;
+// with rk, the rank check above in the same launch.
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr,
-                          int bj, double* M, int64_t ldm, hipStream_t s);
+                          int bj, double* M, int64_t ldm, const RankCheck* rk, hipStream_t s);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 
 // Column permutation of `rows` x (cols col0..) of X given by src_top/dst_low,
 // plus the same permutation of jpvt (int64, may be null).  ncols = columns of

@@ -300,6 +300,13 @@ __global__ __launch_bounds__(256) void qp3_norms_kernel(const double* A, int64_t
   }
 }
 
+size_t qrcp_workspace_bytes(int64_t m, int64_t n, int64_t k) {
+  if (n <= 0 || k <= 0) return 0;
+  const int max_nwg = (int)((m + kQpRows - 1) / kQpRows);
+  const size_t n_part = (size_t)2 * max_nwg * kQpRec;
+  return 2 * padded_bytes(n) + padded_bytes((size_t)64 * n) + padded_bytes(n_part);
+}
+
 }  // namespace rq
 
 using namespace rq;
@@ -323,8 +330,7 @@ extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, i
   if (k == 0) return RQ_OK;
   const int max_nwg = (int)((m + kQpRows - 1) / kQpRows);
   const size_t n_part = (size_t)2 * max_nwg * kQpRec;
-  const size_t need = 2 * padded_bytes(n) + padded_bytes((size_t)64 * n) + padded_bytes(n_part);
-  RQ_TRY(reserve(h, need));
+  RQ_TRY(reserve(h, qrcp_workspace_bytes(m, n, k)));
   Carve cv(h->ws);
   double* vn1 = cv.take<double>(n);
   double* vn2 = cv.take<double>(n);

@@ -49,7 +49,7 @@ FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails va
 
 def test_null_handle_is_argument_one(lib):
     assert lib.rq_destroy(None) == -1
-    assert lib.rqrcp_factor(None, 4, 4, 4, 2, 2, None, 4, None, 4, None, None, None, 2) == -1
+    assert lib.rqrcp_factor(None, 4, 4, 4, 2, 2, None, 4, None, 4, None, None, None, 2, None) == -1
 
 
 @pytest.mark.parametrize("args,code", [
@@ -66,19 +66,19 @@ def test_rqrcp_argument_validation(lib, args, code):
     m, n, k, b, p = args
     buf = ctypes.c_void_p(0x2000)
     rc = lib.rqrcp_factor(FAKE, m, n, k, b, p, buf, max(1, m), buf, max(1, b + p), buf, buf,
-                          None, 0)
+                          None, 0, None)
     assert rc == code
 
 
 def test_rqrcp_leading_dimension_and_pointer_checks(lib):
     buf = ctypes.c_void_p(0x2000)
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, None, 10, buf, 4, buf, buf, None, 0) == -7
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 9, buf, 4, buf, buf, None, 0) == -8
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, None, 4, buf, buf, None, 0) == -9
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 3, buf, buf, None, 0) == -10
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, None, buf, None, 0) == -11
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, buf, None, None, 0) == -12
-    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, buf, buf, buf, 1) == -14
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, None, 10, buf, 4, buf, buf, None, 0, None) == -7
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 9, buf, 4, buf, buf, None, 0, None) == -8
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, None, 4, buf, buf, None, 0, None) == -9
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 3, buf, buf, None, 0, None) == -10
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, None, buf, None, 0, None) == -11
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, buf, None, None, 0, None) == -12
+    assert lib.rqrcp_factor(FAKE, 10, 6, 6, 2, 2, buf, 10, buf, 4, buf, buf, buf, 1, None) == -14
 
 
 def test_sketch_and_sample_qrcp_validation(lib):
@@ -168,3 +168,34 @@ def test_header_compiles_standalone(cmd):
     r = subprocess.run(cmd[:1] + ["-fsyntax-only", "-Wall", "-Wextra", "-Werror"] + cmd[1:] + [HEADER],
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr
+
+
+def test_workspace_query_validation_and_values(lib):
+    """rq_workspace_query touches no device: its argument checks and the sizes it
+    reports are host logic (numbering h=1 op=2 prec=3 m=4 n=5 k=6 b=7 p=8 bytes=9)."""
+    from paper_2008_04447_amd import _lib
+    out = ctypes.c_size_t(0)
+    q = lambda op, m, n, k, b, p, prec=0, o=ctypes.byref(out): lib.rq_workspace_query(
+        FAKE, op, prec, m, n, k, b, p, o)
+    assert lib.rq_workspace_query(None, _lib.RQ_OP_RQRCP, 0, 10, 10, 10, 2, 2, ctypes.byref(out)) == -1
+    assert q(7, 10, 10, 10, 2, 2) == -2
+    assert q(_lib.RQ_OP_RQRCP, 10, 10, 10, 2, 2, prec=5) == -3
+    assert q(_lib.RQ_OP_RQRCP, -1, 10, 10, 2, 2) == -4
+    assert q(_lib.RQ_OP_RQRCP, 10, 65537, 10, 2, 2) == -5
+    assert q(_lib.RQ_OP_RQRCP, 10, 10, 11, 2, 2) == -6
+    assert q(_lib.RQ_OP_RQRCP, 10, 10, 10, 65, 2) == -7
+    assert q(_lib.RQ_OP_RQRCP, 10, 10, 10, 2, 9) == -8          # ell > m
+    assert q(_lib.RQ_OP_RQRCP, 10, 10, 10, 2, 2, o=None) == -9
+    sizes = {}
+    for op in (_lib.RQ_OP_TRQRCP, _lib.RQ_OP_TUXV, _lib.RQ_OP_RQRCP, _lib.RQ_OP_RSRQRCP,
+               _lib.RQ_OP_QRCP, _lib.RQ_OP_SKETCH, _lib.RQ_OP_SAMPLE_QRCP):
+        assert q(op, 2000, 1500, 32, 32, 8) == 0, op
+        sizes[op] = out.value
+        assert out.value > 0, op
+        assert q(op, 2000, 3000, 32, 32, 8) == 0
+        assert out.value > sizes[op], op                      # grows with n
+    # TUXV needs the TRQRCP work plus its own; the sample QRCP needs no records for 0 steps
+    assert sizes[_lib.RQ_OP_TUXV] > sizes[_lib.RQ_OP_TRQRCP]
+    assert q(_lib.RQ_OP_SAMPLE_QRCP, 0, 1500, 0, 32, 8) == 0 and out.value == 0
+    # the 8000 x 8000 factorization (b = 64, p = 8) fits in well under 1 GB
+    assert q(_lib.RQ_OP_RQRCP, 8000, 8000, 8000, 64, 8) == 0 and 0 < out.value < 1 << 30

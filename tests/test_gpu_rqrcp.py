@@ -97,7 +97,7 @@ def test_sample_qrcp_nonfinite_is_reported(api):
 # ----------------------------------------------------------------------------- RQRCP
 def _rqrcp_case(api, m, n, b, p, k, a, om):
     A = _dev(api, a)
-    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, om), b, p, k)
+    jpvt, tau, T, info = api.rqrcp_factor(A, _dev(api, om), b, p, k)
     api.default_handle(0).sync()
     return _host(A), _host(jpvt), _host(tau), _host(T)
 
@@ -110,7 +110,11 @@ def _check_against_oracle(a, om, b, p, k, qr, jpvt, tau, T, min_prefix):
     assert sorted(jpvt) == list(range(n))
     np.testing.assert_array_equal(jpvt[:pre], ref.jpvt[:pre])
     r_g = np.triu(qr[:k])
-    r_o = np.triu(ref.qr[:k])
+    # oracle R with its columns put in the GPU's order (the two permutations
+    # agree on the certified prefix; past it they may order the rest differently)
+    where = np.empty(n, dtype=np.int64)
+    where[ref.jpvt] = np.arange(n)
+    r_o = np.triu(ref.qr[:k])[:, where[jpvt]]
     rows = min(pre, k)
     # Householder rounding errors are absolute (~ eps ||A||), so deep rows of a
     # graded R get the floor 1e-12 ||A||_F on top of the relative 1e-10.
@@ -210,7 +214,7 @@ def test_rqrcp_headline_8000_parity(api, variant):
     a, om = _headline_input(variant)
     print(f"8000^2 {variant}: inputs drawn", flush=True)
     A = _dev(api, a)
-    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, om), b, p)
+    jpvt, tau, T, info = api.rqrcp_factor(A, _dev(api, om), b, p)
     api.default_handle(0).sync()
     jp = _host(jpvt)
     assert np.array_equal(np.sort(jp), np.arange(n))
@@ -269,25 +273,100 @@ def test_rqrcp_known_pivot_family_full_parity(api):
 def test_rqrcp_zero_rank_and_empty(api):
     m, n = 40, 30
     A = _dev(api, np.zeros((m, n)))
-    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, synth.omega(10, m, 1)), 8, 2, k=0)
+    jpvt, tau, T, info = api.rqrcp_factor(A, _dev(api, synth.omega(10, m, 1)), 8, 2, k=0)
     api.default_handle(0).sync()
     np.testing.assert_array_equal(_host(jpvt), np.arange(n))
 
 
-def test_rqrcp_singular_r11_is_reported(api):
-    """An all-zero matrix factored past its first block: R11 = 0, so the sample
-    update of eq. (update1) turns the sample into NaNs.  Later sample QRCPs stop
-    with no admissible pivot; the status bits report it, every access stays in
-    bounds (the column maps left from block 0 are checked) and the zero factor
-    is untouched: no column moves and every tau is zero."""
+def test_rqrcp_all_zero_matrix_falls_back(api):
+    """An all-zero matrix factored past its first block: R_00 = 0, so the rank
+    check fires at column 1 (|R_ii| <= eps max(m, n) |R_00| = 0) and every later
+    sample is a fresh projection of the (zero) trailing matrix instead of
+    eq. (update1), which would divide by R11 = 0.  No status bit is raised, no
+    column moves (all norms tie at zero and the lowest position wins), every
+    tau is zero and the factor stays zero, as in the oracle."""
     m, n, b, p = 120, 90, 16, 8
-    A = _dev(api, np.zeros((m, n)))
-    jpvt, tau, T = api.rqrcp_factor(A, _dev(api, synth.omega(b + p, m, 2)), b, p, k=n)
-    with pytest.raises(api.RQError, match="bits = 6$"):
-        api.default_handle(0).sync()
+    a = np.zeros((m, n))
+    om = synth.omega(b + p, m, 2)
+    A = _dev(api, a)
+    jpvt, tau, T, info = api.rqrcp_factor(A, _dev(api, om), b, p, k=n)
+    api.default_handle(0).sync()
+    ref = oracle.rqrcp(a, om, b, p)
+    assert ref.info == 1 and int(_host(info)[0]) == 1
+    np.testing.assert_array_equal(_host(jpvt), ref.jpvt)
     np.testing.assert_array_equal(_host(jpvt), np.arange(n))
     assert np.all(_host(tau) == 0.0)
     assert np.all(_host(A) == 0.0)
+
+
+@pytest.mark.parametrize("m,n,r,b,p,kind", [
+    (300, 240, 100, 32, 8, "lowrank"),
+    (200, 200, 37, 16, 8, "lowrank"),
+    (120, 90, 50, 16, 8, "zerocols"),
+])
+def test_rqrcp_rank_deficient_matches_oracle(api, m, n, r, b, p, kind):
+    """Exactly rank-r inputs factored to min(m, n).  Eq. (update1) needs R11
+    nonsingular (Section 3.2): in the block holding column r, |R_rr| is at
+    rounding level (exactly zero for zero columns), so both sides record
+    info = r + 1 and take fresh samples of the updated trailing matrix from then
+    on (Section 3.4).  Pivots on the certified prefix and R rows agree with the
+    oracle, the GPU result is a valid pivoted QR on its own
+    (||AP - QR|| / ||A|| <= 1e-13, Q^T Q = I) and no status bit is raised."""
+    if kind == "lowrank":
+        sig = synth.spectrum("pow10", r, scale=r / 6.0)
+        a = synth.low_rank(m, n, sig, 4500 + r, 4501 + r)
+    else:
+        a = synth.gaussian((m, n), 4502)
+        a[:, synth.rng(4503).permutation(n)[:n - r]] = 0.0
+    om = synth.omega(b + p, m, 4504 + r)
+    A = _dev(api, a)
+    jpvt, tau, T, info = api.rqrcp_factor(A, _dev(api, om), b, p)
+    api.default_handle(0).sync()          # raises on any status bit
+    ref = oracle.rqrcp(a, om, b, p)
+    assert ref.info == r + 1
+    assert int(_host(info)[0]) == ref.info
+    qr, jp, ta, tt = _host(A), _host(jpvt), _host(tau), _host(T)
+    assert np.isfinite(qr).all() and np.isfinite(ta).all() and np.isfinite(tt).all()
+    pre = _check_against_oracle(a, om, b, p, min(m, n), qr, jp, ta, tt, min_prefix=16)
+    print(f"rank {r}: info {ref.info}, certified prefix {pre}")
+    if kind == "zerocols":
+        # the zero columns come last and leave an exactly zero trailing block
+        assert set(jp[r:]) == set(np.flatnonzero(~a.any(axis=0)))
+        assert np.all(np.triu(qr)[r:] == 0.0)
+
+
+def test_rqrcp_full_rank_keeps_sample_update(api):
+    """On a full-rank input the rank check never fires: info = 0."""
+    m, n, b, p = 300, 240, 32, 8
+    sig = synth.spectrum("pow10", 240, scale=40.0)
+    a = synth.low_rank(m, n, sig, 85, 86)
+    A = _dev(api, a)
+    jpvt, tau, T, info = api.rqrcp_factor(A, _dev(api, synth.omega(b + p, m, 87)), b, p)
+    api.default_handle(0).sync()
+    assert int(_host(info)[0]) == 0
+
+
+def test_rqrcp_exact_tie_goes_to_lowest_position(api):
+    """A duplicated column of the largest norm gives bitwise-equal sample norms on
+    both sides, an exact tie at the first step, which the lowest current position
+    wins (reading c2).  After it the two sides agree on every step up to the
+    first uncertified one, as they do without a tie."""
+    m, n, b, p = 300, 240, 32, 8
+    a = synth.gaussian((m, n), 11)
+    a[:, 3] *= 10.0
+    a[:, 7] = a[:, 3]
+    om = synth.omega(b + p, m, 12)
+    qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, n, a, om)
+    ref = oracle.rqrcp(a, om, b, p)
+    assert ref.trace.best[0] == ref.trace.second[0]
+    assert jpvt[0] == 3 and ref.jpvt[0] == 3
+    cert = ref.trace.certified(ref.sample_scale, REL, ABS)
+    bad = np.flatnonzero(~cert[1:])
+    run = 1 + (int(bad[0]) if bad.size else cert.size - 1)
+    assert run >= 16
+    np.testing.assert_array_equal(jpvt[:run], ref.jpvt[:run])
+    q = q_from_inplace(qr, tau)
+    assert np.linalg.norm(a[:, jpvt] - q @ np.triu(qr)) / np.linalg.norm(a) <= 1e-13
 
 
 def test_rqrcp_deterministic(api):

@@ -90,7 +90,7 @@ def test_rsrqrcp_first_block_equals_rqrcp(api):
     qr, jpvt, tau, T, _ = _run(api, a, b, p, 96, 4601)
     full, _ = _omegas(b + p, m, 1, 4601)
     A = api.colmajor(a, device=torch.device("cuda", 0))
-    jp2, tau2, _ = api.rqrcp_factor(A, api.colmajor(full[0], device=torch.device("cuda", 0)), b, p, 96)
+    jp2, tau2, _, _ = api.rqrcp_factor(A, api.colmajor(full[0], device=torch.device("cuda", 0)), b, p, 96)
     api.default_handle(0).sync()
     np.testing.assert_array_equal(jpvt[:b], _host(jp2)[:b])
     np.testing.assert_array_equal(tau[:b], _host(tau2)[:b])
