@@ -241,13 +241,18 @@ rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64
  *  X, ldx    out: k x k double upper triangular (ldx >= k).
  *  V, ldv    out: n x k double with orthonormal columns (ldv >= n).
  *  jpvt      out[n]: TRQRCP's column permutation.
+ *  sigma     out[k] or NULL: the singular values of X, largest first (the SVD
+ *            of the small factor, Section 4.2, which estimates the leading
+ *            singular values of A; the diagonal of X gives the cruder QLP
+ *            estimates).  Computed on the device as rq_singular_values does;
+ *            k <= RQ_MAX_SVD when sigma is requested, else RQ_E_UNSUPPORTED.
  * Argument numbers: h=1 prec=2 m=3 n=4 k=5 b=6 p=7 A=8 lda=9 Omega=10 ldo=11
- * U=12 ldu=13 X=14 ldx=15 V=16 ldv=17 jpvt=18.
+ * U=12 ldu=13 X=14 ldx=15 V=16 ldv=17 jpvt=18 sigma=19.
  */
 rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
                    int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
                    double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
-                   int64_t* jpvt);
+                   int64_t* jpvt, double* sigma);
 
 /*
  * tuxv_svd_iter -- TUXV with jmax >= 1 alternations (Algorithm 6, Section
@@ -257,12 +262,26 @@ rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, i
  * even jmax.  Every step is one more pass over A (two for U^T A when k > 64:
  * its rows are formed in chunks of 64); in mixed precision the products with
  * A use BF16 operands and FP32 accumulation like the first step.
- * Same arguments and results as tuxv_svd, plus jmax (argument 19, >= 1).
+ * Same arguments and results as tuxv_svd (sigma: the singular values of the
+ * final X), plus jmax (argument 20, >= 1).
  */
 rq_status tuxv_svd_iter(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
                         int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
                         double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
-                        int64_t* jpvt, int64_t jmax);
+                        int64_t* jpvt, double* sigma, int64_t jmax);
+
+/*
+ * rq_singular_values -- singular values of a k x k matrix X (device, ld ldx,
+ * not modified) into sigma[k] (device), largest first: Householder
+ * bidiagonalization in one workgroup, then bisection with Sturm counts on the
+ * Golub-Kahan tridiagonal of the bidiagonal factor, one wave per singular
+ * value.  The computed values are those of X + dX with ||dX|| = O(k eps ||X||)
+ * (as for LAPACK's bidiagonal route).  Used by tuxv_svd for sigma.
+ * Limit: k <= RQ_MAX_SVD, else RQ_E_UNSUPPORTED.
+ * Argument numbers: h=1 k=2 X=3 ldx=4 sigma=5.
+ */
+#define RQ_MAX_SVD 1024
+rq_status rq_singular_values(rq_handle h, int64_t k, const double* X, int64_t ldx, double* sigma);
 
 /*
  * rq_sketch -- the sketch B = Omega A alone (the first step of Algorithms 3-5).

@@ -34,10 +34,11 @@ SIGNATURES = {
                                          c_p, c_i64, c_p, c_i64, c_p, c_p, c_i64, c_p, c_i64,
                                          c_p, c_i64]),
     "tuxv_svd": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_i64, c_i64, c_p,
-                                  c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p]),
+                                  c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p, c_p]),
     "tuxv_svd_iter": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_i64, c_i64, c_p,
                                        c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p,
-                                       c_i64]),
+                                       c_p, c_i64]),
+    "rq_singular_values": (ctypes.c_int32, [c_p, c_i64, c_p, c_i64, c_p]),
     "rq_sketch": (ctypes.c_int32, [c_p, ctypes.c_int, c_i64, c_i64, c_i64, c_p, c_i64, c_p,
                                    c_i64, c_p, c_i64]),
     "rq_sample_qrcp": (ctypes.c_int32, [c_p, c_i64, c_i64, c_i64, c_p, c_i64, c_p]),

@@ -196,9 +196,10 @@ def trqrcp_truncate(A, Omega, b, p, k, handle=None):
     return jpvt, Y, T, R
 
 
-def tuxv_svd(A, Omega, b, p, k, handle=None, jmax=1):
+def tuxv_svd(A, Omega, b, p, k, handle=None, jmax=1, sigma=False):
     """TUXV (Algorithm 6, jmax alternations).  Returns (U, X, V, jpvt) with
-    A ~ U X V^T (X upper for odd jmax, lower for even)."""
+    A ~ U X V^T (X upper for odd jmax, lower for even); with sigma=True also the
+    singular values of X (largest first, computed on the device) as a fifth item."""
     h = handle or default_handle(A.device.index)
     m, n = A.shape
     dev = A.device
@@ -207,16 +208,29 @@ def tuxv_svd(A, Omega, b, p, k, handle=None, jmax=1):
     X = empty_colmajor(k, k, torch.float64, dev)
     V = empty_colmajor(n, k, torch.float64, dev)
     jpvt = torch.empty(max(n, 1), dtype=torch.int64, device=dev)[:n]
+    sv = torch.empty(max(k, 1), dtype=torch.float64, device=dev)[:k] if sigma else None
     if jmax == 1:
         rc = _lib.load().tuxv_svd(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
                                   ld(Omega), _ptr(U), ld(U), _ptr(X), ld(X), _ptr(V), ld(V),
-                                  _ptr(jpvt))
+                                  _ptr(jpvt), _ptr(sv))
     else:
         rc = _lib.load().tuxv_svd_iter(h.ptr, prec, m, n, k, b, p, _ptr(A), ld(A), _ptr(Omega),
                                        ld(Omega), _ptr(U), ld(U), _ptr(X), ld(X), _ptr(V), ld(V),
-                                       _ptr(jpvt), int(jmax))
+                                       _ptr(jpvt), _ptr(sv), int(jmax))
     _check("tuxv_svd", rc, h)
-    return U, X, V, jpvt
+    return (U, X, V, jpvt, sv) if sigma else (U, X, V, jpvt)
+
+
+def singular_values(X, handle=None):
+    """Singular values (largest first) of the square float64 device matrix X."""
+    h = handle or default_handle(X.device.index)
+    k = X.shape[0]
+    if X.shape[1] != k:
+        raise ValueError("X must be square")
+    sv = torch.empty(max(k, 1), dtype=torch.float64, device=X.device)[:k]
+    rc = _lib.load().rq_singular_values(h.ptr, k, _ptr(X), ld(X), _ptr(sv))
+    _check("rq_singular_values", rc, h)
+    return sv
 
 
 def sketch(Omega, A, handle=None):

@@ -31,6 +31,7 @@ enum KClass {
   K_OTHER,
   K_SKETCH_BF16,    // mixed precision: B = Omega A with BF16 operands
   K_INNER_BF16,     // mixed precision: products over A with BF16 operands
+  K_SVD,            // singular values of a small square matrix (TUXV's X)
   K_NUM_CLASSES
 };
 
@@ -38,7 +39,7 @@ inline const char* kclass_name(int c) {
   static const char* names[K_NUM_CLASSES] = {
       "sketch", "sample_qrcp", "permute", "panel", "inner_products", "reduce",
       "trailing_update", "omega11", "sample_update", "qp3_pivot", "qp3_gemv", "qp3_row",
-      "tr_select", "tr_rows", "tr_small", "other", "sketch_bf16", "inner_products_bf16"};
+      "tr_select", "tr_rows", "tr_small", "other", "sketch_bf16", "inner_products_bf16", "svd"};
   return (c >= 0 && c < K_NUM_CLASSES) ? names[c] : "?";
 }
 
@@ -188,5 +189,10 @@ size_t rqrcp_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t b, int64_t
 size_t qrcp_workspace_bytes(int64_t m, int64_t n, int64_t k);
 size_t sketch_workspace_bytes(int64_t ell, int64_t m, int64_t n);
 size_t sample_qrcp_workspace_bytes(int64_t ell, int64_t n);
+size_t singular_values_workspace_bytes(int64_t k);
+// Singular values of the k x k matrix X (ld ldx), largest first, into sigma
+// (k <= RQ_MAX_SVD); `work` holds singular_values_workspace_bytes(k).
+rq_status run_singular_values(rq_handle h, int64_t k, const double* X, int64_t ldx, double* sigma,
+                              double* work);
 
 }  // namespace rq

@@ -109,7 +109,7 @@ rq_status launch(rq_server s, Req& q) {
                          o1, r.k, o2, r.k);
   else
     rc = tuxv_svd(h, (rq_prec)r.prec, r.m, r.n, r.k, r.b, r.p, A, r.m, Om, ell, o0, r.m, o1, r.k, o2,
-                  r.n, jp);
+                  r.n, jp, nullptr);
   if (rc != RQ_OK) return rc;
   if (r.jpvt) RQ_CHECK(h, hipMemcpyAsync(r.jpvt, jp, (size_t)r.n * 8, hipMemcpyDeviceToHost, st));
   if (r.out0) RQ_CHECK(h, hipMemcpyAsync(r.out0, o0, (size_t)r.m * r.k * 8, hipMemcpyDeviceToHost, st));

@@ -340,7 +340,8 @@ static size_t tuxv_extra_bytes(int64_t m, int64_t n, int64_t k) {
   return padded_bytes((size_t)m * k) + padded_bytes((size_t)k * k) + padded_bytes((size_t)k * n) +
          padded_bytes((size_t)n * k) + padded_bytes((size_t)m * k) + 2 * padded_bytes((size_t)64 * k) +
          padded_bytes((size_t)k + 64) +
-         padded_bytes(vstage_doubles(n, k)) + padded_bytes((size_t)std::max(n, k));
+         padded_bytes(vstage_doubles(n, k)) + padded_bytes((size_t)std::max(n, k)) +
+         (k <= RQ_MAX_SVD ? singular_values_workspace_bytes(k) : 0);
 }
 
 size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv) {
@@ -404,7 +405,7 @@ extern "C" rq_status trqrcp_truncate(rq_handle h, rq_prec prec, int64_t m, int64
 static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k, int64_t b,
                            int64_t p, const void* A, int64_t lda, const double* Omega, int64_t ldo,
                            double* U, int64_t ldu, double* X, int64_t ldx, double* V, int64_t ldv,
-                           int64_t* jpvt, int64_t jmax) {
+                           int64_t* jpvt, double* sigma, int64_t jmax) {
   RQ_TRY(check_common(h, prec, m, n, k, b, p, A, lda, Omega, ldo));
   if (!valid_ptr(U, m * k)) return -12;
   if (ldu < std::max<int64_t>(1, m)) return -13;
@@ -413,6 +414,7 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
   if (!valid_ptr(V, n * k)) return -16;
   if (ldv < std::max<int64_t>(1, n)) return -17;
   if (!valid_ptr(jpvt, n)) return -18;
+  if (sigma && k > RQ_MAX_SVD) return RQ_E_UNSUPPORTED;
   if (n == 0 || k == 0) {
     if (n > 0) RQ_CHECK(h, launch_iota(jpvt, (int)n, h->stream));
     return RQ_OK;
@@ -435,6 +437,7 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
   double* tauq = cv.take<double>((size_t)k + 64);
   double* vstage = cv.take<double>(vstage_doubles(n, k));                             // V staged
   int64_t* ident = cv.take<int64_t>((size_t)std::max(n, k));                          // 0, 1, 2, ...
+  double* svdw = k <= RQ_MAX_SVD ? cv.take<double>(singular_values_workspace_bytes(k) / 8) : nullptr;
   const bool f32 = prec == RQ_MIXED_BF16;
   hipStream_t s = h->stream;
   // 1. TRQRCP: A P ~ Q R
@@ -510,22 +513,26 @@ static rq_status tuxv_core(rq_handle h, rq_prec prec, int64_t m, int64_t n, int6
     RQ_TRY(form_q(h, Z0T, n, n, k, Tb, V, ldv, w));
     if (j + 1 == jmax) break;
   }
+  // 7. singular values of X (the SVD of the small factor, Section 4.2)
+  if (sigma) RQ_TRY(run_singular_values(h, k, X, ldx, sigma, svdw));
   return RQ_OK;
 }
 
 extern "C" rq_status tuxv_svd(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
                               int64_t b, int64_t p, const void* A, int64_t lda,
                               const double* Omega, int64_t ldo, double* U, int64_t ldu, double* X,
-                              int64_t ldx, double* V, int64_t ldv, int64_t* jpvt) {
-  return tuxv_core(h, prec, m, n, k, b, p, A, lda, Omega, ldo, U, ldu, X, ldx, V, ldv, jpvt, 1);
+                              int64_t ldx, double* V, int64_t ldv, int64_t* jpvt, double* sigma) {
+  return tuxv_core(h, prec, m, n, k, b, p, A, lda, Omega, ldo, U, ldu, X, ldx, V, ldv, jpvt, sigma,
+                   1);
 }
 
 extern "C" rq_status tuxv_svd_iter(rq_handle h, rq_prec prec, int64_t m, int64_t n, int64_t k,
                                    int64_t b, int64_t p, const void* A, int64_t lda,
                                    const double* Omega, int64_t ldo, double* U, int64_t ldu,
                                    double* X, int64_t ldx, double* V, int64_t ldv, int64_t* jpvt,
-                                   int64_t jmax) {
+                                   double* sigma, int64_t jmax) {
   if (!h) return -1;
-  if (jmax < 1) return -19;
-  return tuxv_core(h, prec, m, n, k, b, p, A, lda, Omega, ldo, U, ldu, X, ldx, V, ldv, jpvt, jmax);
+  if (jmax < 1) return -20;
+  return tuxv_core(h, prec, m, n, k, b, p, A, lda, Omega, ldo, U, ldu, X, ldx, V, ldv, jpvt, sigma,
+                   jmax);
 }

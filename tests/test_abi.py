@@ -104,11 +104,24 @@ def test_rsrqrcp_argument_numbering(lib):
     assert lib.rsrqrcp_factor(*args, buf, 4, 40, buf, buf, buf, 1) == -15
 
 
-def test_tuxv_iter_jmax_is_argument_19(lib):
+def test_tuxv_iter_jmax_is_argument_20(lib):
     buf = ctypes.c_void_p(0x2000)
-    args = (0, 10, 8, 4, 2, 2, buf, 10, buf, 4, buf, 10, buf, 4, buf, 8, buf)
+    args = (0, 10, 8, 4, 2, 2, buf, 10, buf, 4, buf, 10, buf, 4, buf, 8, buf, None)
     assert lib.tuxv_svd_iter(None, *args, 1) == -1
-    assert lib.tuxv_svd_iter(FAKE, *args, 0) == -19
+    assert lib.tuxv_svd_iter(FAKE, *args, 0) == -20
+
+
+def test_singular_values_validation(lib):
+    buf = ctypes.c_void_p(0x2000)
+    assert lib.rq_singular_values(None, 4, buf, 4, buf) == -1
+    assert lib.rq_singular_values(FAKE, -1, buf, 4, buf) == -2
+    assert lib.rq_singular_values(FAKE, 4, None, 4, buf) == -3
+    assert lib.rq_singular_values(FAKE, 4, buf, 3, buf) == -4
+    assert lib.rq_singular_values(FAKE, 4, buf, 4, None) == -5
+    assert lib.rq_singular_values(FAKE, 1025, buf, 1025, buf) == 1003
+    # sigma of more than RQ_MAX_SVD values is refused before any work
+    args = (0, 3000, 2000, 1025, 64, 8, buf, 3000, buf, 72, buf, 3000, buf, 1025, buf, 2000, buf)
+    assert lib.tuxv_svd(FAKE, *args, buf) == 1003
 
 
 def test_noalloc_argument_validation(lib):
