@@ -365,11 +365,23 @@ rq_status rq_profile_get(rq_handle h, int32_t index, const char** name, int64_t*
  *
  * Request data lives in host memory owned by the caller, which must stay valid
  * until the request completes: A (m x n, column-major, leading dimension m;
- * float for RQ_MIXED_BF16, double for RQ_FP64) and Omega (ell x m, leading
- * dimension ell) are copied in (page-locked memory keeps the copies
+ * float for RQ_MIXED_BF16 and RQ_AUTO, double for RQ_FP64) and Omega (ell x m,
+ * leading dimension ell) are copied in (page-locked memory keeps the copies
  * asynchronous); outputs are copied back to non-NULL host pointers:
  *   TRQRCP: jpvt[n], out0 = Y (m x k), out1 = T (k x k), out2 = R (k x n);
- *   TUXV:   jpvt[n], out0 = U (m x k), out1 = X (k x k), out2 = V (n x k).
+ *   TUXV:   jpvt[n], out0 = U (m x k), out1 = X (k x k), out2 = V (n x k),
+ *           sigma[k] = the singular values of X (computed only when non-NULL).
+ *
+ * Precision per request.  RQ_FP64 and RQ_MIXED_BF16 run as named.  RQ_AUTO
+ * (A in float) lets the server choose from the accuracy the caller needs, tol
+ * (> 0, the relative truncation error ||A - approximation||_F / ||A||_F the
+ * request expects): BF16 operands round A by a relative 2^-9 on average, and
+ * that noise reaches the rank-k result through k of min(m, n) directions, so
+ * the mixed path adds an error of about f = 1.5 * 2^-9 * sqrt(k / min(m, n))
+ * to the optimum e in quadrature.  The request runs on BF16 MFMA when
+ * f <= 0.3 tol (then sqrt(e^2 + f^2) <= 1.05 e for e >= tol) and otherwise in
+ * FP64, with A widened to double on the device (rq_serve_route reports the
+ * choice for given sizes; rq_result.prec_used the one taken).
  * Latency runs from rq_serve_submit to the moment the scheduler sees the
  * request's completion event (host copies included).
  * rq_serve_stop finishes every submitted request, then frees everything.
@@ -380,9 +392,11 @@ typedef struct rq_server_s* rq_server;
 
 enum { RQ_REQ_QUEUED = 0, RQ_REQ_RUNNING = 1, RQ_REQ_DONE = 2, RQ_REQ_FAILED = 3 };
 
+enum { RQ_AUTO = 2 };      /* request precision: chosen from tol (above)  */
+
 typedef struct {
   int32_t op;             /* RQ_OP_TRQRCP or RQ_OP_TUXV                    */
-  int32_t prec;           /* rq_prec                                       */
+  int32_t prec;           /* RQ_FP64, RQ_MIXED_BF16 or RQ_AUTO             */
   int64_t m, n, k, b, p;  /* as trqrcp_truncate                            */
   const void* A;          /* host, m x n                                   */
   const double* Omega;    /* host, (b + p) x m                             */
@@ -390,6 +404,8 @@ typedef struct {
   double* out0;
   double* out1;
   double* out2;
+  double* sigma;          /* TUXV only: host out[k] or NULL                */
+  double tol;             /* RQ_AUTO: required relative error (> 0)        */
 } rq_request;
 
 typedef struct {
@@ -399,7 +415,13 @@ typedef struct {
   double queue_ms;        /* submit -> admission                           */
   double latency_ms;      /* submit -> completion observed                 */
   double flops;           /* algorithmic flop count of the request         */
+  int32_t prec_used;      /* RQ_FP64 or RQ_MIXED_BF16: what ran            */
+  int32_t reserved;
 } rq_result;
+
+/* The arithmetic a request of these sizes and prec/tol runs in (RQ_FP64 or
+ * RQ_MIXED_BF16), by the rule above; -1 for an invalid prec or tol. */
+int32_t rq_serve_route(int32_t prec, int64_t m, int64_t n, int64_t k, double tol);
 
 rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t max_m,
                          int64_t max_n, int64_t max_k, int64_t max_ell, rq_server* server);

@@ -59,6 +59,7 @@ SIGNATURES = {
     "rq_serve_stats": (ctypes.c_int32, [c_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                                         ctypes.POINTER(ctypes.c_int32)]),
     "rq_serve_stop": (ctypes.c_int32, [c_p]),
+    "rq_serve_route": (ctypes.c_int32, [ctypes.c_int32, c_i64, c_i64, c_i64, ctypes.c_double]),
 }
 
 
@@ -66,14 +67,16 @@ class Request(ctypes.Structure):
     """Mirror of rq_request (include/rqrcp.h)."""
     _fields_ = [("op", ctypes.c_int32), ("prec", ctypes.c_int32), ("m", c_i64), ("n", c_i64),
                 ("k", c_i64), ("b", c_i64), ("p", c_i64), ("A", c_p), ("Omega", c_p),
-                ("jpvt", c_p), ("out0", c_p), ("out1", c_p), ("out2", c_p)]
+                ("jpvt", c_p), ("out0", c_p), ("out1", c_p), ("out2", c_p), ("sigma", c_p),
+                ("tol", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
     """Mirror of rq_result (include/rqrcp.h)."""
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("device_error", c_i64),
                 ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("prec_used", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 RQ_OP_TRQRCP = 0
@@ -93,6 +96,7 @@ RQ_E_UNSUPPORTED = 1003
 RQ_E_DEVICE = 1004
 RQ_FP64 = 0
 RQ_MIXED_BF16 = 1
+RQ_AUTO = 2
 
 _lib = None
 

@@ -266,6 +266,11 @@ def sample_qrcp_noalloc(B, steps, perm, handle=None):
 
 
 # ----------------------------------------------------------------------------- serving
+def serve_route(prec, m, n, k, tol):
+    """The arithmetic (RQ_FP64 or RQ_MIXED_BF16) the server runs such a request in."""
+    return _lib.load().rq_serve_route(int(prec), m, n, k, float(tol))
+
+
 def pinned_empty(shape, dtype):
     """Page-locked host array in column-major order (asynchronous copies)."""
     tdt = {np.float32: torch.float32, np.float64: torch.float64, np.int64: torch.int64}[dtype]
@@ -286,13 +291,19 @@ class Server:
                                                     max_k, max_ell, ctypes.byref(self.ptr)))
         self._keep = {}
 
-    def submit(self, op, A, Omega, b, p, k, outputs=True):
-        """A, Omega: column-major host arrays (float32 A = mixed BF16, float64 A = FP64)."""
+    def submit(self, op, A, Omega, b, p, k, outputs=True, tol=None, sigma=False):
+        """A, Omega: column-major host arrays.  float64 A runs in FP64; float32 A
+        runs on BF16 MFMA, or, with ``tol`` (the relative error the request
+        needs), in whichever arithmetic rq_serve_route picks (RQ_AUTO).  With
+        sigma=True a TUXV request also returns the singular values of X."""
         lib = _lib.load()
         m, n = A.shape
         if not A.flags.f_contiguous or not Omega.flags.f_contiguous:
             raise ValueError("A and Omega must be column-major (Fortran order)")
-        prec = RQ_MIXED_BF16 if A.dtype == np.float32 else RQ_FP64
+        if A.dtype == np.float64:
+            prec = RQ_FP64
+        else:
+            prec = _lib.RQ_AUTO if tol is not None else RQ_MIXED_BF16
         outs = None
         if outputs:
             if op == _lib.RQ_OP_TRQRCP:
@@ -301,23 +312,28 @@ class Server:
             else:
                 outs = (pinned_empty((n,), np.int64), pinned_empty((m, k), np.float64),
                         pinned_empty((k, k), np.float64), pinned_empty((n, k), np.float64))
+        sv = pinned_empty((k,), np.float64) if (sigma and op == _lib.RQ_OP_TUXV) else None
         req = _lib.Request(op, prec, m, n, k, b, p, A.ctypes.data, Omega.ctypes.data,
                            outs[0].ctypes.data if outs else None,
                            outs[1].ctypes.data if outs else None,
                            outs[2].ctypes.data if outs else None,
-                           outs[3].ctypes.data if outs else None)
+                           outs[3].ctypes.data if outs else None,
+                           sv.ctypes.data if sv is not None else None,
+                           float(tol) if tol is not None else 0.0)
         rid = ctypes.c_uint64()
         rc = lib.rq_serve_submit(self.ptr, ctypes.byref(req), ctypes.byref(rid))
         if rc != 0:
             raise RQError("rq_serve_submit", rc)
-        self._keep[rid.value] = (A, Omega, outs)
+        self._keep[rid.value] = (A, Omega, outs, sv)
         return rid.value
 
     def _result(self, fn, rid):
         res = _lib.Result()
         _check(fn.__name__, fn(self.ptr, rid, ctypes.byref(res)))
         d = {f: getattr(res, f) for f, _ in _lib.Result._fields_}
-        d["outputs"] = self._keep.get(rid, (None, None, None))[2]
+        keep = self._keep.get(rid, (None, None, None, None))
+        d["outputs"] = keep[2]
+        d["sigma"] = keep[3]
         return d
 
     def poll(self, rid):
@@ -331,6 +347,10 @@ class Server:
         _check("rq_serve_stats", _lib.load().rq_serve_stats(self.ptr, ctypes.byref(c),
                                                              ctypes.byref(pb), ctypes.byref(pr)))
         return {"completed": c.value, "peak_bytes": pb.value, "peak_running": pr.value}
+
+    def release(self, rid):
+        """Drop the binding's references to a finished request's host buffers."""
+        self._keep.pop(rid, None)
 
     def stop(self):
         if self.ptr:

@@ -1131,6 +1131,17 @@ hipError_t launch_iota(int64_t* v, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void cast_f32_f64_kernel(const float* src, double* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cast_f32_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                     dst, n);
+  return hipGetLastError();
+}
+
 __global__ void set_i64_kernel(int64_t* p, int64_t v) {
   if (threadIdx.x == 0) *p = v;
 }

@@ -164,6 +164,8 @@ struct RankCheck {
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr,
                           int bj, double* M, int64_t ldm, const RankCheck* rk, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+// dst[i] = (double)src[i] for i < n (contiguous arrays).
+hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 
 // Column permutation of `rows` x (cols col0..) of X given by src_top/dst_low,
 // plus the same permutation of jpvt (int64, may be null).  ncols = columns of

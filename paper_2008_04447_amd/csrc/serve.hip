@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <mutex>
 #include <thread>
@@ -26,17 +27,28 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 struct Req {
   rq_request r;
+  int32_t route = RQ_FP64;     // the arithmetic it runs in
   Clock::time_point t_submit, t_admit;
   rq_result res{};
   size_t off = 0, footprint = 0;
   int slot = -1;
 };
 
-size_t elem_bytes(int32_t prec) { return prec == RQ_MIXED_BF16 ? 4 : 8; }
+// host element size of A
+size_t elem_bytes(int32_t prec) { return prec == RQ_FP64 ? 8 : 4; }
 
-size_t footprint_of(const rq_request& r) {
+// RQ_AUTO requests that run in FP64 hold A twice on the device: as copied in
+// (float) and widened to double.
+size_t a_bytes(const rq_request& r, int32_t route) {
+  const size_t mn = (size_t)r.m * r.n;
+  size_t b = rq::Arena::round(mn * elem_bytes(r.prec));
+  if (r.prec == RQ_AUTO && route == RQ_FP64) b += rq::Arena::round(mn * 8);
+  return b;
+}
+
+size_t footprint_of(const rq_request& r, int32_t route) {
   const size_t ell = (size_t)(r.b + r.p);
-  size_t b = rq::Arena::round((size_t)r.m * r.n * elem_bytes(r.prec));
+  size_t b = a_bytes(r, route);
   b += rq::Arena::round(ell * r.m * 8);
   b += rq::Arena::round((size_t)r.n * 8);                  // jpvt
   if (r.op == RQ_OP_TRQRCP)
@@ -44,7 +56,8 @@ size_t footprint_of(const rq_request& r) {
          rq::Arena::round((size_t)r.k * r.n * 8);
   else
     b += rq::Arena::round((size_t)r.m * r.k * 8) + rq::Arena::round((size_t)r.k * r.k * 8) +
-         rq::Arena::round((size_t)r.n * r.k * 8);
+         rq::Arena::round((size_t)r.n * r.k * 8) +
+         (r.sigma ? rq::Arena::round((size_t)r.k * 8) : 0);
   return b;
 }
 
@@ -95,22 +108,31 @@ rq_status launch(rq_server s, Req& q) {
     return p;
   };
   const int64_t ell = r.b + r.p;
-  void* A = take((size_t)r.m * r.n * elem_bytes(r.prec));
+  const size_t mn = (size_t)r.m * r.n;
+  void* A = take(mn * elem_bytes(r.prec));
+  const bool widen = r.prec == RQ_AUTO && q.route == RQ_FP64;
+  double* A64 = widen ? reinterpret_cast<double*>(take(mn * 8)) : nullptr;
   double* Om = reinterpret_cast<double*>(take((size_t)ell * r.m * 8));
   int64_t* jp = reinterpret_cast<int64_t*>(take((size_t)r.n * 8));
   double* o0 = reinterpret_cast<double*>(take((size_t)r.m * r.k * 8));
   double* o1 = reinterpret_cast<double*>(take((size_t)r.k * r.k * 8));
   double* o2 = reinterpret_cast<double*>(take((size_t)std::max(r.k * r.n, r.n * r.k) * 8));
-  RQ_CHECK(h, hipMemcpyAsync(A, r.A, (size_t)r.m * r.n * elem_bytes(r.prec), hipMemcpyHostToDevice, st));
+  double* sv = (r.op == RQ_OP_TUXV && r.sigma) ? reinterpret_cast<double*>(take((size_t)r.k * 8))
+                                               : nullptr;
+  RQ_CHECK(h, hipMemcpyAsync(A, r.A, mn * elem_bytes(r.prec), hipMemcpyHostToDevice, st));
   RQ_CHECK(h, hipMemcpyAsync(Om, r.Omega, (size_t)ell * r.m * 8, hipMemcpyHostToDevice, st));
+  if (widen) RQ_CHECK(h, rq::launch_cast_f32_f64(static_cast<const float*>(A), A64, (int64_t)mn, st));
+  const void* Arun = widen ? A64 : A;
+  const rq_prec prun = (rq_prec)q.route;
   rq_status rc;
   if (r.op == RQ_OP_TRQRCP)
-    rc = trqrcp_truncate(h, (rq_prec)r.prec, r.m, r.n, r.k, r.b, r.p, A, r.m, Om, ell, jp, o0, r.m,
-                         o1, r.k, o2, r.k);
+    rc = trqrcp_truncate(h, prun, r.m, r.n, r.k, r.b, r.p, Arun, r.m, Om, ell, jp, o0, r.m, o1,
+                         r.k, o2, r.k);
   else
-    rc = tuxv_svd(h, (rq_prec)r.prec, r.m, r.n, r.k, r.b, r.p, A, r.m, Om, ell, o0, r.m, o1, r.k, o2,
-                  r.n, jp, nullptr);
+    rc = tuxv_svd(h, prun, r.m, r.n, r.k, r.b, r.p, Arun, r.m, Om, ell, o0, r.m, o1, r.k, o2, r.n,
+                  jp, sv);
   if (rc != RQ_OK) return rc;
+  if (sv) RQ_CHECK(h, hipMemcpyAsync(r.sigma, sv, (size_t)r.k * 8, hipMemcpyDeviceToHost, st));
   if (r.jpvt) RQ_CHECK(h, hipMemcpyAsync(r.jpvt, jp, (size_t)r.n * 8, hipMemcpyDeviceToHost, st));
   if (r.out0) RQ_CHECK(h, hipMemcpyAsync(r.out0, o0, (size_t)r.m * r.k * 8, hipMemcpyDeviceToHost, st));
   if (r.out1) RQ_CHECK(h, hipMemcpyAsync(r.out1, o1, (size_t)r.k * r.k * 8, hipMemcpyDeviceToHost, st));
@@ -186,6 +208,14 @@ using namespace rq;
 
 extern "C" {
 
+int32_t rq_serve_route(int32_t prec, int64_t m, int64_t n, int64_t k, double tol) {
+  if (prec == RQ_FP64 || prec == RQ_MIXED_BF16) return prec;
+  if (prec != RQ_AUTO || !(tol > 0.0) || !(tol < HUGE_VAL) || m < 1 || n < 1 || k < 1) return -1;
+  // BF16 rounding noise of A seen through k of min(m, n) directions
+  const double floor_bf16 = 1.5 * std::ldexp(1.0, -9) * std::sqrt((double)k / (double)std::min(m, n));
+  return floor_bf16 <= 0.3 * tol ? RQ_MIXED_BF16 : RQ_FP64;
+}
+
 rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t max_m,
                          int64_t max_n, int64_t max_k, int64_t max_ell, rq_server* out) {
   int count = 0;
@@ -249,21 +279,24 @@ rq_status rq_serve_start(int device, size_t budget_bytes, int32_t slots, int64_t
 rq_status rq_serve_submit(rq_server s, const rq_request* r, uint64_t* id) {
   if (!s) return -1;
   if (!r || (r->op != RQ_OP_TRQRCP && r->op != RQ_OP_TUXV) ||
-      (r->prec != RQ_FP64 && r->prec != RQ_MIXED_BF16) || r->m < 1 || r->n < 1 || r->k < 1 ||
+      rq_serve_route(r->prec, r->m, r->n, r->k, r->tol) < 0 || r->m < 1 || r->n < 1 || r->k < 1 ||
       r->k > std::min(r->m, r->n) || r->b < 1 || r->b > RQ_MAX_B || r->p < 0 ||
       r->b + r->p > RQ_MAX_ELL || r->b + r->p > r->m || !r->A || !r->Omega)
     return -2;
   if (!id) return -3;
   if (r->m > s->max_m || r->n > s->max_n || r->k > s->max_k || r->b + r->p > s->max_ell)
     return RQ_E_UNSUPPORTED;
+  if (r->op == RQ_OP_TUXV && r->sigma && r->k > RQ_MAX_SVD) return RQ_E_UNSUPPORTED;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) return RQ_E_UNSUPPORTED;
   const uint64_t nid = s->next_id++;
   Req q;
   q.r = *r;
+  q.route = rq_serve_route(r->prec, r->m, r->n, r->k, r->tol);
   q.t_submit = Clock::now();
-  q.footprint = footprint_of(*r);
+  q.footprint = footprint_of(*r, q.route);
   q.res.state = RQ_REQ_QUEUED;
+  q.res.prec_used = q.route;
   q.res.flops = flops_of(*r);
   if (!s->adm->enqueue(nid, q.footprint)) return RQ_E_UNSUPPORTED;
   s->reqs.emplace(nid, q);

@@ -109,6 +109,43 @@ def graded_known_pivots(m: int, n: int, seed: int, decay: float = 4.0, eta: floa
     return np.asfortranarray(a), perm
 
 
+def dct_basis(n: int, r: int) -> np.ndarray:
+    """n x r orthonormal DCT-II basis vectors: column i samples cos(pi i (j + 1/2) / n),
+    so the first columns vary smoothly with the row index j."""
+    from scipy.fft import idct
+    return np.asfortranarray(idct(np.eye(n)[:, :r], axis=0, norm="ortho"))
+
+
+def smooth_columns(m: int, n: int, sigma: np.ndarray, seed: int, device=None):
+    """Matrix whose neighbouring columns are strongly correlated, like the images
+    and discretized fields of the paper's quality experiment: A = U diag(sigma) V^T
+    diag(env) with U Haar (m x r), V the first r DCT-II basis vectors of length n
+    (smooth in the column index) and a seeded smooth column envelope
+    env_j = 1 + 0.6 sin(6 pi j / n + phi).  Column norms then cluster, so ordering
+    columns by norm alone picks near-duplicates.  With ``device`` the result is a
+    column-major float64 torch tensor (U drawn with torch's seeded generator)."""
+    r = len(sigma)
+    v = dct_basis(n, r)
+    phi = rng(seed + 3).uniform(0.0, 2.0 * np.pi)
+    env = 1.0 + 0.6 * np.sin(6.0 * np.pi * np.arange(n) / n + phi)
+    if device is None:
+        u = haar(m, r, seed)
+        return np.asfortranarray(((u * sigma[None, :]) @ v.T) * env[None, :])
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    x = torch.randn((m, r), generator=g, dtype=torch.float64, device=device)
+    q, rr = torch.linalg.qr(x, mode="reduced")
+    d = torch.sign(torch.diagonal(rr))
+    d[d == 0] = 1.0
+    u = q * d[None, :] * torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)[None, :]
+    a = (u @ torch.from_numpy(np.ascontiguousarray(v.T)).to(device)) * \
+        torch.from_numpy(env).to(device)[None, :]
+    out = torch.empty((n, m), dtype=torch.float64, device=device).t()
+    out.copy_(a)
+    return out
+
+
 def workload(config: int, small: bool = False):
     """Concrete input of one benchmark/parity configuration.
 

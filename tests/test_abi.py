@@ -212,3 +212,26 @@ def test_workspace_query_validation_and_values(lib):
     assert q(_lib.RQ_OP_SAMPLE_QRCP, 0, 1500, 0, 32, 8) == 0 and out.value == 0
     # the 8000 x 8000 factorization (b = 64, p = 8) fits in well under 1 GB
     assert q(_lib.RQ_OP_RQRCP, 8000, 8000, 8000, 64, 8) == 0 and 0 < out.value < 1 << 30
+
+
+def test_serve_route_rule(lib):
+    """The per-request precision rule of the serving loop (host logic): BF16 when
+    its rounding floor 1.5 * 2^-9 * sqrt(k / min(m, n)) is at most 0.3 tol."""
+    from paper_2008_04447_amd import _lib
+    route = lib.rq_serve_route
+    assert route(_lib.RQ_FP64, 100, 100, 10, 0.0) == _lib.RQ_FP64
+    assert route(_lib.RQ_MIXED_BF16, 100, 100, 10, 0.0) == _lib.RQ_MIXED_BF16
+    assert route(_lib.RQ_AUTO, 100, 100, 10, 0.0) == -1          # tol required
+    assert route(_lib.RQ_AUTO, 100, 100, 10, float("nan")) == -1
+    assert route(7, 100, 100, 10, 0.1) == -1
+    # sigma_i = 10^(-i/50): the optimal relative error at rank k is 10^(-k/50)
+    tol = lambda k: 10.0 ** (-k / 50.0)
+    assert route(_lib.RQ_AUTO, 2000, 2000, 16, tol(16)) == _lib.RQ_MIXED_BF16
+    assert route(_lib.RQ_AUTO, 2000, 2000, 64, tol(64)) == _lib.RQ_MIXED_BF16
+    assert route(_lib.RQ_AUTO, 2000, 2000, 128, tol(128)) == _lib.RQ_MIXED_BF16
+    assert route(_lib.RQ_AUTO, 1000, 3000, 128, tol(128)) == _lib.RQ_FP64     # min(m, n) small
+    assert route(_lib.RQ_AUTO, 4096, 4096, 256, tol(256)) == _lib.RQ_FP64
+    f = lambda k, nn: 1.5 * 2.0 ** -9 * (k / nn) ** 0.5
+    for k, nn in [(16, 256), (64, 700), (128, 1614), (128, 1613), (256, 4096)]:
+        want = _lib.RQ_MIXED_BF16 if f(k, nn) <= 0.3 * tol(k) else _lib.RQ_FP64
+        assert route(_lib.RQ_AUTO, nn, nn + 5, k, tol(k)) == want
