@@ -22,23 +22,24 @@ RQ_DEV void raise_status(int64_t* status, int64_t bits) {
 // ends in about a second with an error flag instead of hanging the device.
 constexpr uint32_t kSpinLimit = 1u << 20;
 
-// Cross-workgroup barrier for persistent kernels whose workgroups are all
-// resident.  `counter` starts at 0 for the launch; barrier number `idx`
-// (0-based) completes when the counter reaches nwg * (idx + 1).  Every
-// workgroup calls it the same number of times with all of its threads.
+// Cross-workgroup barrier for kernels whose workgroups are all resident.  Each
+// of the nwg workgroups adds one arrival to `counter` and the barrier completes
+// when the counter reaches `target`: the caller keeps count of the arrivals of
+// earlier barriers on the same counter (zeroed once before the first), so
+// consecutive launches need no reset in between.  A single workgroup neither
+// arrives nor waits.  Every workgroup calls it with all of its threads.
 // The workgroup first synchronizes internally (which orders its threads'
 // global writes before thread 0's), then thread 0 alone performs the
 // device-scope release, the arrival and the bounded wait, and one device-scope
 // acquire before the workgroup proceeds.  With a single workgroup the internal
 // synchronization is all that is needed.  Returns false when the wait timed out
 // or another workgroup aborted; the caller must then leave the kernel.
-RQ_DEV bool grid_barrier(uint32_t* counter, uint32_t* abort_flag, uint32_t nwg, uint32_t idx,
+RQ_DEV bool grid_barrier(uint32_t* counter, uint32_t* abort_flag, uint32_t nwg, uint32_t target,
                          int64_t* status) {
   __shared__ int s_ok;
   __syncthreads();
   if (nwg == 1) return true;
   if (threadIdx.x == 0) {
-    const uint32_t target = nwg * (idx + 1u);
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     uint32_t it = 0;

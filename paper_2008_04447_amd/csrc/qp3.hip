@@ -20,7 +20,7 @@
 
 namespace rq {
 
-constexpr int kQpThreads = 1024;
+constexpr int kQpThreads = 256;
 constexpr int kQpRows = 256;                // rows of column j handled by one workgroup
 
 struct Qp3Args {
@@ -34,6 +34,7 @@ struct Qp3Args {
   double* Wt;         // inner products, Wt[q + c * 64]
   double* part;       // per-workgroup partials: [2][nwg][72] (norm, alpha, u_q)
   uint32_t* counter;
+  uint32_t bar_target;  // counter value at which this column's barrier completes
   uint32_t* abort_flag;
   double* tau;
   int64_t* status;
@@ -53,11 +54,11 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
   const int i = a.i, j = a.j, jb = j - i;
   const int wg = blockIdx.x;
   if (prior_timeout(a.status)) return;
-  __shared__ double s_wv[16];
-  __shared__ int s_wp[16];
+  constexpr int kWaves = kQpThreads / 64;
+  __shared__ double s_wv[kWaves];
+  __shared__ int s_wp[kWaves];
   __shared__ double s_w[64];
-  __shared__ double s_x[kQpRows];
-  __shared__ double s_red[16][64];
+  __shared__ double s_red[kWaves];
   __shared__ int s_piv;
   __shared__ double s_sc[3];
   // 1. argmax of the trailing norms (identical in every workgroup)
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
   if (t == 0) {
     double v = s_wv[0];
     int p = s_wp[0];
-    for (int w = 1; w < 16; ++w)
+    for (int w = 1; w < kWaves; ++w)
       if (better(s_wv[w], s_wp[w], v, p)) {
         v = s_wv[w];
         p = s_wp[w];
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
   __syncthreads();   // s_w is read by every wave below
   // 3. own rows of column j (after the swap), brought up to date
   const int r = j + wg * kQpRows + t;
-  const bool mine = t < kQpRows && r < a.m;
+  const bool mine = r < a.m;
   double x = 0.0;
   if (mine) {
     x = a.A[r + (int64_t)p * a.lda];
@@ -114,16 +115,16 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
   }
   double ss = (mine && r > j) ? x * x : 0.0;
   ss = wave_sum(ss);
-  if (lane == 0) s_red[wave][0] = ss;
+  if (lane == 0) s_red[wave] = ss;
   __syncthreads();
   double* rec = a.part + (int64_t)wg * kQpRec;
   if (t == 0) {
-    double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += s_red[w][0];
-    rec[0] = s;
+    double sacc = 0.0;
+    for (int w = 0; w < kWaves; ++w) sacc += s_red[w];
+    rec[0] = sacc;
     rec[1] = (wg == 0) ? x : 0.0;          // row j lives in workgroup 0, thread 0
   }
-  if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, 0u, a.status)) return;
+  if (!grid_barrier(a.counter, a.abort_flag, (uint32_t)a.nwg, a.bar_target, a.status)) return;
   // Every workgroup has finished reading the norms and W^T(:, p), so workgroup 0
   // may now swap the per-column metadata.
   if (wg == 0 && p != j) {
@@ -144,10 +145,12 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
       a.jpvt[p] = q;
     }
   }
-  // 4. reflector, identical in every workgroup (fixed-order sum of partials)
-  if (t == 0) {
-    double tail = 0.0;
-    for (int w = 0; w < a.nwg; ++w) tail += a.part[(int64_t)w * kQpRec];
+  // 4. reflector, identical in every workgroup (the partials summed in the
+  // same fixed order everywhere)
+  if (wave == 0) {
+    double part = 0.0;
+    for (int w = lane; w < a.nwg; w += 64) part += a.part[(int64_t)w * kQpRec];
+    const double tail = wave_sum(part);
     const double alpha = a.part[1];
     const double s2 = tail + alpha * alpha;
     double beta = 0.0, tau = 0.0, scale = 0.0;
@@ -157,9 +160,11 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
       scale = 1.0 / (alpha - beta);
       tau = (beta - alpha) / beta;
     }
-    s_sc[0] = beta;
-    s_sc[1] = tau;
-    s_sc[2] = scale;
+    if (lane == 0) {
+      s_sc[0] = beta;
+      s_sc[1] = tau;
+      s_sc[2] = scale;
+    }
   }
   __syncthreads();
   const double beta = s_sc[0], tau = s_sc[1], scale = s_sc[2];
@@ -168,31 +173,34 @@ __global__ __launch_bounds__(kQpThreads) void qp3_pivot_kernel(Qp3Args a) {
     v = (r == j) ? 1.0 : x * scale;
     a.A[r + (int64_t)j * a.lda] = (r == j) ? beta : v;
   }
-  if (t < kQpRows) s_x[t] = v;
   if (wg == 0 && t == 0) a.tau[j] = tau;
-  __syncthreads();
-  // 5. partial u_q = sum over own rows of Y(r, q) v(r), q < jb
-  {
-    const int g = t & 15, q = t >> 4;        // 16 row groups x 64 reflectors
-    double acc = 0.0;
-    if (q < jb) {
-      for (int rr = g; rr < kQpRows; rr += 16) {
-        const int row = j + wg * kQpRows + rr;
-        if (row < a.m) acc += a.A[row + (int64_t)(i + q) * a.lda] * s_x[rr];
-      }
-    }
-    s_red[g][q] = acc;
-  }
-  __syncthreads();
+  // 5. partial u_q = sum over own rows of Y(r, q) v(r), q < jb: wave w takes
+  // reflectors w, w + 4, ... over the workgroup's rows (lane l: rows l, l + 64, ...)
   double* rec2 = a.part + ((int64_t)a.nwg + wg) * kQpRec;
-  if (t < 64) {
-    double s = 0.0;
-    for (int g = 0; g < 16; ++g) s += s_red[g][t];
-    rec2[t] = (t < jb) ? s : 0.0;
+  {
+    __shared__ double s_v[kQpRows];
+    s_v[t] = v;
+    __syncthreads();
+    for (int q = wave; q < 64; q += kWaves) {
+      double acc = 0.0;
+      if (q < jb) {
+#pragma unroll
+        for (int h = 0; h < kQpRows / 64; ++h) {
+          const int row = j + wg * kQpRows + lane + 64 * h;
+          if (row < a.m) acc = fma(a.A[row + (int64_t)(i + q) * a.lda], s_v[lane + 64 * h], acc);
+        }
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) rec2[q] = acc;
+    }
   }
 }
 
-// One wave per trailing column (4 columns per wave, 16 per workgroup).
+// Four trailing columns per workgroup.  The four waves split the rows (wave w
+// takes the 64-row chunks w, w + 4, ...) so that every column is streamed by
+// the whole workgroup with 16 loads in flight per wave; the partial inner
+// products are combined in LDS in a fixed order and wave w then finishes
+// column w (row update and norm downdate).
 __global__ __launch_bounds__(256) void qp3_gemv_kernel(Qp3Args a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = a.i, j = a.j, jb = j - i;
@@ -200,43 +208,50 @@ __global__ __launch_bounds__(256) void qp3_gemv_kernel(Qp3Args a) {
   const double* v = a.A + (int64_t)j * a.lda;   // v(j) = 1 implied, tails below
   const double tol = 1.4901161193847656e-08;    // sqrt(eps): downdate reliability bound
   __shared__ double s_u[64];
+  __shared__ double s_dot[4][4];
   if (threadIdx.x < 64) {
     double s = 0.0;
     if ((int)threadIdx.x < jb)
       for (int w = 0; w < a.nwg; ++w) s += a.part[((int64_t)a.nwg + w) * kQpRec + threadIdx.x];
     s_u[threadIdx.x] = s;
   }
-  __syncthreads();
-  // the four columns of this wave stream together so v is read once for them
-  const int c0 = j + 1 + blockIdx.x * 16 + wave * 4;
-  double dots[4];
+  const int c0 = j + 1 + blockIdx.x * 4;
   {
     const double* cols[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) cols[s] = a.A + (int64_t)min(c0 + s, a.n - 1) * a.lda;
-    double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    int r = j + 1 + lane;
-    for (; r + 64 < a.m; r += 128) {
-      const double v0 = v[r], v1 = v[r + 64];
+    double acc[4][4] = {};
+    int r = j + 1 + wave * 64 + lane;
+    for (; r + 768 < a.m; r += 1024) {
+      double vv[4], xx[4][4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        acc[s][0] += v0 * cols[s][r];
-        acc[s][1] += v1 * cols[s][r + 64];
-      }
+      for (int h = 0; h < 4; ++h) vv[h] = v[r + 256 * h];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) xx[s][h] = cols[s][r + 256 * h];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) acc[s][h] = fma(vv[h], xx[s][h], acc[s][h]);
     }
-    if (r < a.m) {
+    for (; r < a.m; r += 256) {
       const double v0 = v[r];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s][0] += v0 * cols[s][r];
+      for (int s = 0; s < 4; ++s) acc[s][0] = fma(v0, cols[s][r], acc[s][0]);
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) dots[s] = wave_sum(acc[s][0] + acc[s][1]);
+    for (int s = 0; s < 4; ++s) {
+      const double d = wave_sum((acc[s][0] + acc[s][1]) + (acc[s][2] + acc[s][3]));
+      if (lane == 0) s_dot[wave][s] = d;
+    }
   }
-  for (int s = 0; s < 4; ++s) {
-    const int c = c0 + s;
-    if (c >= a.n) break;
+  __syncthreads();
+  const int s = wave;
+  const int c = c0 + s;
+  if (c < a.n) {
     const double* col = a.A + (int64_t)c * a.lda;
-    const double dot = dots[s] + col[j];
+    const double dot = ((s_dot[0][s] + s_dot[1][s]) + (s_dot[2][s] + s_dot[3][s])) + col[j];
     double corr = 0.0, yw = 0.0;
     if (lane < jb) {
       const double wq = a.Wt[lane + (int64_t)c * 64];
@@ -356,6 +371,10 @@ extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, i
   a.abort_flag = h->sync + 1;
   a.tau = tau;
   a.status = h->status;
+  // the pivot steps' barrier counter and abort flag start at zero; each step's
+  // barrier then completes at the running arrival count (no reset in between)
+  RQ_CHECK(h, launch_zero_u32(h->sync, 2, s));
+  uint32_t arrivals = 0;
   for (int64_t i = 0; i < k; i += nb) {
     const int64_t iend = std::min(k, i + nb);
     a.i = (int)i;
@@ -366,7 +385,8 @@ extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, i
         KTimer kt(h, K_QP3_PIVOT, 4.0 * (m - j) * (jb + 1),
                   8.0 * ((double)(m - j) * (jb + 2) + 2.0 * m));
         a.nwg = (int)((m - j + kQpRows - 1) / kQpRows);
-        RQ_CHECK(h, launch_zero_u32(h->sync, 2, s));
+        if (a.nwg > 1) arrivals += (uint32_t)a.nwg;
+        a.bar_target = arrivals;
         hipLaunchKernelGGL(qp3_pivot_kernel, dim3(a.nwg), dim3(kQpThreads), 0, s, a);
         RQ_CHECK(h, hipGetLastError());
       }
@@ -374,7 +394,7 @@ extern "C" rq_status qrcp_factor(rq_handle h, int64_t m, int64_t n, int64_t k, i
       if (nt > 0) {
         KTimer kt(h, K_QP3_GEMV, 2.0 * (m - j) * (double)nt,
                   8.0 * ((double)(m - j) * nt + (double)(m - j)));
-        hipLaunchKernelGGL(qp3_gemv_kernel, dim3((unsigned)((nt + 15) / 16)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(qp3_gemv_kernel, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, s, a);
         RQ_CHECK(h, hipGetLastError());
       }
     }
