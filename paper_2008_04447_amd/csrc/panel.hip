@@ -514,6 +514,16 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
           em = (v > em || v != v) ? v : em;
         }
       }
+      // The offset is about kappa^2 eps.  Beyond 1e-4 (kappa of the panel
+      // beyond about 7e5, which the diagonal ratio of the first factor does not
+      // bound, as for Kahan-like columns) the two passes lose accuracy in R
+      // (about 3e-10 relative at kappa = 1e8): every workgroup sees the same G
+      // and leaves the panel untouched for the column-by-column route, as when
+      // the first factorization fails.
+      if (__syncthreads_or(!(em <= 1e-4))) {
+        if (wg == 0 && t == 0) *a.fallback = 1u;
+        return;
+      }
       // Within 64 eps of the identity, Q1 is already orthonormal to working
       // precision: Q = Q1 and R = R1 (R2 taken as I, its product skipped).
       const bool ident = !__syncthreads_or(!(em <= 64.0 * 2.220446049250313e-16));
@@ -547,8 +557,11 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
           D[e] = dv;
         }
         __syncthreads();
-      } else if (!chol_inv(G, D, diag, bj, t) && t == 0) {
-        raise_status(a.status, kErrNonFinite);
+      } else if (!chol_inv(G, D, diag, bj, t)) {
+        // the second factorization failed (the same G, so the same outcome, in
+        // every workgroup): the column-by-column route factors the panel
+        if (wg == 0 && t == 0) *a.fallback = 1u;
+        return;
       }
       if (!ident) tile_times(x, X, D, t, rbase, 0);              // Q = Q1 R2^{-1}
       if (wg == 0) {

@@ -13,6 +13,7 @@ import pytest
 import oracle
 import synth
 from test_gpu_rqrcp import ABS, REL, _check_against_oracle, _rqrcp_case, api  # noqa: F401  (fixture)
+from tests.helpers import q_from_inplace
 
 pytestmark = pytest.mark.gpu
 
@@ -132,3 +133,49 @@ def test_second_pass_routes(api, kappa):
     assert ratios[0] <= GATE / 2, ratios            # the Cholesky-QR route in every case
     qr, jpvt, tau, T = _rqrcp_case(api, m, n, b, p, k, a, om)
     _check_tall(a, om, b, p, k, qr, jpvt, tau, T)
+
+
+def _kahan(n, theta, pert):
+    """Kahan's matrix diag(s^j (1 - pert j)) (I - c striu(ones)), c = cos theta,
+    s = sin theta: QRCP keeps its column order, the diagonal of R decays only
+    geometrically, yet kappa grows like (1 + c)^n."""
+    c, s = np.cos(theta), np.sin(theta)
+    k = np.eye(n) - c * np.triu(np.ones((n, n)), 1)
+    return np.diag(s ** np.arange(n) * (1.0 - pert * np.arange(n))) @ k
+
+
+@pytest.mark.parametrize("theta", [1.3, 1.2, 1.15])
+def test_kahan_panel_falls_back(api, theta):
+    """Kahan-like panels (kappa 1e8 .. 3e12) whose first Cholesky factor has a
+    small diagonal ratio (10 .. 3000), so the diagonal gate lets them into the
+    Cholesky-QR route: the first pass's offset max|Q1^T Q1 - I| (1e-2 .. 1,
+    beyond the 1e-4 limit) sends them to the column-by-column route (a failed
+    second Cholesky would too).  With Omega = I (ell = m) the sample QRCP is
+    QRCP itself.  Checked is what a backward-stable route guarantees whatever
+    kappa: the GPU's own residual and orthogonality, and T.  R and the late
+    pivots of such a panel are only determined to about kappa eps (its forward
+    condition): the pivots must agree over the first half, and while they
+    agree the R rows, matched by column, within 1e-10 ||R_i|| + 64 kappa eps ||A||."""
+    m, b, p = 96, 64, 32
+    a = np.asfortranarray(synth.haar(m, 64, 5300) @ _kahan(64, theta, 1e-7))
+    om = np.eye(m)
+    ratios = _panel_diag_ratios(a, om, b, p, 64)
+    assert ratios[0] <= GATE / 4, ratios          # the diagonal gate admits the panel
+    qr, jpvt, tau, T = _rqrcp_case(api, m, 64, b, p, 64, a, om)
+    ref = oracle.rqrcp(a, om, b, p)
+    np.testing.assert_array_equal(jpvt[:32], ref.jpvt[:32])
+    q = q_from_inplace(qr, tau)
+    r = np.triu(qr)
+    assert np.linalg.norm(a[:, jpvt] - q @ r) / np.linalg.norm(a) <= 1e-13
+    assert np.linalg.norm(q.T @ q - np.eye(m), 2) <= 1e-13
+    diff = np.flatnonzero(jpvt != ref.jpvt)
+    rows = int(diff[0]) if diff.size else 64
+    where = np.empty(64, dtype=np.int64)
+    where[ref.jpvt] = np.arange(64)
+    r_ref = np.triu(ref.qr)[:64]
+    kappa = np.linalg.cond(r_ref)
+    d = np.linalg.norm(r[:rows] - r_ref[:rows, where[jpvt]], axis=1)
+    assert np.all(d <= 1e-10 * np.linalg.norm(r_ref[:rows], axis=1)
+                  + 64 * kappa * np.finfo(float).eps * np.linalg.norm(a))
+    np.testing.assert_allclose(T[:64, :64], oracle.form_t(oracle.unit_lower(qr, 64), tau),
+                               atol=1e-12)
