@@ -170,7 +170,7 @@ static int64_t panel_prep_words(int64_t M, int bj);
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm, hipEvent_t queued, double* panel_rec,
-                          int64_t panel_m, int panel_bj) {
+                          int64_t panel_m, int panel_bj, int groups) {
   const int lm = sq_lm(ell);
   SqArgs a{};
   a.B = B;
@@ -178,7 +178,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.ell = ell;
   a.N = (int)N;
   a.steps = steps;
-  a.nwg = sq_groups(N, h->max_groups);
+  a.nwg = sq_groups(N, groups > 0 ? groups : h->max_groups);
   a.rec = w.rec;
   a.rs = sq_record_stride(lm);
   a.counter = h->sync;

@@ -170,10 +170,13 @@ size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
 // kernel launch (work that waits on it becomes ready together with the launch).
 // `panel_rec`, when given, is the record area of the panel that follows (M
 // rows, bj columns): it is prepared together with the sample's records, and
-// that panel is then run with `prepared` set.
+// that panel is then run with `prepared` set.  `groups` is the workgroup
+// allowance of the launch (0: the handle's max_groups, which leaves compute
+// units to the RQRCP side stream).
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm, hipEvent_t queued = nullptr,
-                          double* panel_rec = nullptr, int64_t panel_m = 0, int panel_bj = 0);
+                          double* panel_rec = nullptr, int64_t panel_m = 0, int panel_bj = 0,
+                          int groups = 0);
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt,
                     bool prepared = false);

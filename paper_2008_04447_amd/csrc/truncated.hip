@@ -121,8 +121,11 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
   for (int64_t col0 = 0; col0 < k; col0 += b) {
     const int bj = (int)std::min<int64_t>(b, k - col0);
     const int64_t N = n - col0, M = m - col0, Nt = N - bj;
-    // 1. sample pivots
-    RQ_TRY(run_sample_qrcp(h, w.sample + col0 * ell, ell, ell, N, bj, w.sw, nullptr));
+    // 1. sample pivots (nothing runs beside them: the launch may take every
+    //    compute unit the handle's launches may fill)
+    RQ_TRY(run_sample_qrcp(h, w.sample + col0 * ell, ell, ell, N, bj, w.sw, /*perm=*/nullptr,
+                           /*queued=*/nullptr, /*panel_rec=*/nullptr, /*panel_m=*/0,
+                           /*panel_bj=*/0, /*groups=*/h->update_wgs));
     // 2. permute the index map, W^T and the finished R rows (A is not moved)
     {
       KTimer kt(h, K_PERMUTE, 0.0, 32.0 * bj * (double)(2 * col0 + 1));
