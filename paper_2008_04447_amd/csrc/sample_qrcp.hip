@@ -9,16 +9,18 @@
 // 2-norm over all workgroups, so every step has one cross-workgroup exchange:
 // each workgroup publishes a record for its best column (see the published
 // records in device_common.hpp) holding (norm^2, position, tau, beta) and the
-// Householder vector that column would define, so that whichever record wins,
-// every workgroup can apply the reflection straight from it.  Norms of rows
-// j+1.. are recomputed from the transformed columns (no downdating).  Ties go
-// to the lowest current position; positions follow the transpositions
-// j <-> p_j.
+// Householder vector that column would define.  Every workgroup polls the
+// heads (norm^2, position) of all records, which go out first, finds the
+// winner and then reads that one record's tau, beta and vector, so the step
+// moves two round trips of small reads (fetching every record whole in one
+// round trip moved 40 KB per workgroup and step and measured slower).  Norms
+// of rows j+1.. are recomputed from the transformed columns (no downdating).
+// Ties go to the lowest current position; positions follow the
+// transpositions j <-> p_j.
 //
 // Work that is the same for the whole workgroup (its record, the winner) is
-// done by wave 0 alone while the other waves fetch the records into LDS: with
-// four waves per SIMD, repeating it in every wave would cost four times its
-// latency on every step.
+// done by wave 0 alone: with several waves per SIMD, repeating it in every
+// wave would cost several times its latency on every step.
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "rqrcp.h"
@@ -28,14 +30,9 @@ namespace rq {
 constexpr int kHead = 4;                        // record head: norm^2, position, tau, beta
 constexpr int kHeadPer = 4;                     // record heads one lane of wave 0 polls
 
-// Workgroup of NT threads: waves 1.. (NT - 64 threads) fetch the records, each
-// polling at most kPoll words; kSpecCap record words fit the one-round fetch.
 template <int NT>
 struct SqShape {
   static constexpr int kWaves = NT / 64;
-  static constexpr int kPollers = NT - 64;
-  static constexpr int kPoll = NT >= 1024 ? 8 : 12;
-  static constexpr int kSpecCap = kPollers * kPoll;
 };
 static_assert(kHeadPer * 64 >= RQ_MAX_N / 256, "every workgroup's head is polled");
 
@@ -45,38 +42,6 @@ RQ_DEV double column_sum(double v) {
   v = quad_sum(v);
   if (Q == 8) v += dpp_f64<kDppHalfMirror>(v);
   return v;
-}
-
-// Waves 1..: wait until the words u, u + kPollers, ... (< total) of a step's
-// records are published, then copy them to s_all.  False when the wait gave up.
-template <int NT>
-RQ_DEV bool poll_records(const double* rj, int total, const SqArgs& a, int u, double* s_all) {
-  constexpr int kPoll = SqShape<NT>::kPoll, kPollers = SqShape<NT>::kPollers;
-  unsigned long long b[kPoll];
-#pragma unroll
-  for (int k = 0; k < kPoll; ++k) {
-    const int e = u + k * kPollers;
-    b[k] = (e < total) ? peek(rj + e) : 0ull;
-  }
-  uint32_t it = 0;
-  while (true) {
-    bool all = true;
-#pragma unroll
-    for (int k = 0; k < kPoll; ++k) all = all && b[k] != kUnpublished;
-    if (all) break;
-    if (!keep_waiting(it, a.abort_flag, a.status)) return false;
-#pragma unroll
-    for (int k = 0; k < kPoll; ++k) {
-      const int e = u + k * kPollers;
-      if (e < total && b[k] == kUnpublished) b[k] = peek(rj + e);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kPoll; ++k) {
-    const int e = u + k * kPollers;
-    if (e < total) s_all[e] = __longlong_as_double((long long)b[k]);
-  }
-  return true;
 }
 
 // Wave 0: the winner (norm^2 v, position p, workgroup w) over the heads of all
@@ -133,7 +98,6 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
   constexpr int kQ = Q;                        // lanes per column
   constexpr int kSqCols = NT / kQ;             // columns per workgroup
   constexpr int kSqWaves = SqShape<NT>::kWaves;
-  constexpr int kSpecCap = SqShape<NT>::kSpecCap;
   constexpr int RPL = LM / kQ;                 // rows per lane
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -148,8 +112,8 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
   __shared__ double s_wv[kSqWaves];
   __shared__ int s_wp[kSqWaves];
   __shared__ double s_cand[kSqWaves][LM];      // each wave's best column
-  __shared__ double s_all[kSpecCap];           // the step's records
-  __shared__ int s_hp[2];                      // winner position, its record
+  __shared__ double s_rec[kHead + LM];         // the winner's record (words 2..)
+  __shared__ int s_hp;                         // winner position
 
   double x[RPL];
 #pragma unroll
@@ -172,10 +136,6 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
   int pos = own ? c : INT_MAX;
   bool active = own;
   bool flagged = false;
-  // All records of a step are fetched into LDS when they fit (one round trip);
-  // otherwise wave 0 fetches the winner's record once it is known.
-  const bool spec = a.nwg * a.rs <= kSpecCap;
-
   for (int j = 0; j < a.steps; ++j) {
     // ---- each wave's best column (its values go to LDS) ---------------------
     // All kQ lanes of a column hold bitwise the same norm (see column_sum), so
@@ -201,11 +161,18 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
     bool ok = true;
     if (wave == 0) {
       // ---- the workgroup's best column and its reflector, published --------
+      // The head (norm^2, position), which every workgroup polls to find the
+      // winner, goes out first; tau, beta and the vector follow while the
+      // other records are still arriving (only the winner's are read).
       double v = (lane < kSqWaves) ? s_wv[lane] : -1.0;
       int p = (lane < kSqWaves) ? s_wp[lane] : INT_MAX;
       int w = lane;
       row0_argmax(v, p, w);
       double* rec = a.rec + ((int64_t)j * a.nwg + wg) * a.rs;
+      if (lane == 0) {
+        publish(rec, v);
+        publish(rec + 1, (double)p);
+      }
       double beta = 0.0, scale = 0.0, tau = 0.0;
       if (p != INT_MAX) {
         // v is the sum of squares of the column's rows j.., the s2 of its reflector
@@ -218,16 +185,14 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       if (lane == 0) {
         publish(rec + 2, tau);
         publish(rec + 3, beta);
-        publish(rec, v);
-        publish(rec + 1, (double)p);
       }
       // ---- the winner over all workgroups, from the record heads ----------
       double wv;
       int wp, ww;
       ok = poll_winner(rj, a, lane, wv, wp, ww);
-      if (__builtin_amdgcn_ballot_w64(!ok) == 0 && wp != INT_MAX && !spec) {
-        // the records did not fit in LDS: fetch the winner's record
-        for (int r = lane; r < a.rs && ok; r += 64) {
+      if (__builtin_amdgcn_ballot_w64(!ok) == 0 && wp != INT_MAX) {
+        // fetch the winner's tau, beta and vector (words 2.. of its record)
+        for (int r = 2 + lane; r < a.rs && ok; r += 64) {
           const double* src = rj + (int64_t)ww * a.rs + r;
           unsigned long long bt = peek(src);
           uint32_t it = 0;
@@ -238,26 +203,19 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
             }
             bt = peek(src);
           }
-          s_all[r] = __longlong_as_double((long long)bt);
+          s_rec[r] = __longlong_as_double((long long)bt);
         }
-        ww = 0;
       }
-      if (lane == 0) {
-        s_hp[0] = wp;
-        s_hp[1] = ww;
-      }
-    } else if (spec) {
-      ok = poll_records<NT>(rj, a.nwg * a.rs, a, t - 64, s_all);
+      if (lane == 0) s_hp = wp;
     }
     if (__syncthreads_or(!ok)) return;
-    const int wpos = s_hp[0];
+    const int wpos = s_hp;
     if (wpos == INT_MAX) {          // every workgroup sees the same: consistent exit
       if (t == 0 && wg == 0) raise_status(a.status, kErrNoPivot);
       return;
     }
-    const double* hrec = s_all + (spec ? s_hp[1] * a.rs : 0);   // winner's record
-    const double tau = hrec[2], beta = hrec[3];
-    const double* vh = hrec + kHead;                            // its Householder vector
+    const double tau = s_rec[2], beta = s_rec[3];
+    const double* vh = s_rec + kHead;                           // the winner's Householder vector
     // ---- positions: j <-> wpos ----------------------------------------------
     if (active) {
       if (pos == wpos) {
@@ -302,9 +260,9 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       nu2 = column_sum<kQ>(n0 + n1);
     }
     // No barrier here: the next step rewrites s_wv, s_wp and s_cand only after
-    // this step's second barrier (wave 0 read them before it), s_all only
-    // after its own first barrier (which follows this step's last read of
-    // s_all), and s_hp before its own second barrier.
+    // this step's second barrier (wave 0 read them before it), and s_rec and
+    // s_hp only after its own first barrier, which follows this step's last
+    // read of them.
   }
   // Every workgroup loaded its columns before the first barrier, so the
   // in-place write of the permuted sample cannot overwrite unread input.
