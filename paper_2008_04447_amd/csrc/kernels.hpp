@@ -10,7 +10,7 @@ struct SqArgs {
   double* B;           // ell x N sample, column-major, leading dimension ldb
   int64_t ldb;
   int ell, N, steps, nwg;
-  double* rec;         // exchange records [steps][nwg][rs], unpublished at launch
+  double* rec;         // exchange records: per step nwg x rs words (heads, then bodies), unpublished at launch
   int rs;
   uint32_t* counter;   // zeroed before launch
   uint32_t* abort_flag;
@@ -21,8 +21,8 @@ struct SqArgs {
 };
 int sq_lm(int ell);    // padded register height used for a given ell (0 = unsupported)
 int sq_record_stride(int lm);
-// Workgroups of the sample QRCP kernel for N columns: 128 columns per workgroup
-// (8 lanes each) when that needs at most max_groups, else 256 (4 lanes each).
+// Workgroups of the sample QRCP kernel for N columns: 64 columns per workgroup
+// when that needs at most max_groups, else 128, else 256 (4 lanes per column).
 int sq_groups(int64_t N, int max_groups);
 int sq_max_groups(int64_t N);   // upper bound of sq_groups over max_groups (record sizing)
 hipError_t launch_sample_qrcp(const SqArgs& a, int lm, hipStream_t s);

@@ -2,10 +2,11 @@
 //
 // Each sample column is held in registers by a group of Q = 4 lanes for the
 // whole kernel: lane q of the group keeps rows q, q+4, q+8, ... (ell <= 96,
-// padded with zero rows); a workgroup of 512 threads holds 128 columns, or of
-// 1024 threads 256 columns for very wide samples (two waves per SIMD where
-// possible: the reflection is issue-bound, and four waves per SIMD would queue
-// behind each other on every step).  A pivot step needs the column of largest trailing
+// padded with zero rows); a workgroup of 256 threads holds 64 columns (one
+// wave per SIMD), or of 512 or 1024 threads 128 or 256 columns when the
+// launch's workgroup allowance calls for fewer, wider workgroups (the
+// reflection is issue-bound: waves that share a SIMD queue behind each other on
+// every step).  A pivot step needs the column of largest trailing
 // 2-norm over all workgroups, so every step has one cross-workgroup exchange:
 // each workgroup publishes a record for its best column (see the published
 // records in device_common.hpp) holding (norm^2, position, tau, beta) and the
@@ -27,7 +28,7 @@
 
 namespace rq {
 
-constexpr int kHead = 4;                        // record head: norm^2, position, tau, beta
+constexpr int kHead = 4;                        // record words besides the vector: norm^2, position, tau, beta
 constexpr int kHeadPer = 4;                     // record heads one lane of wave 0 polls
 
 template <int NT>
@@ -52,8 +53,8 @@ RQ_DEV bool poll_winner(const double* rj, const SqArgs& a, int lane, double& v, 
 #pragma unroll
   for (int k = 0; k < kHeadPer; ++k) {
     const int g = lane + 64 * k;
-    hv[k] = (g < a.nwg) ? peek(rj + (int64_t)g * a.rs) : 0ull;
-    hp[k] = (g < a.nwg) ? peek(rj + (int64_t)g * a.rs + 1) : 0ull;
+    hv[k] = (g < a.nwg) ? peek(rj + 2 * g) : 0ull;
+    hp[k] = (g < a.nwg) ? peek(rj + 2 * g + 1) : 0ull;
   }
   bool ok = true;
   uint32_t it = 0;
@@ -69,8 +70,8 @@ RQ_DEV bool poll_winner(const double* rj, const SqArgs& a, int lane, double& v, 
 #pragma unroll
     for (int k = 0; k < kHeadPer; ++k) {
       const int g = lane + 64 * k;
-      if (g < a.nwg && hv[k] == kUnpublished) hv[k] = peek(rj + (int64_t)g * a.rs);
-      if (g < a.nwg && hp[k] == kUnpublished) hp[k] = peek(rj + (int64_t)g * a.rs + 1);
+      if (g < a.nwg && hv[k] == kUnpublished) hv[k] = peek(rj + 2 * g);
+      if (g < a.nwg && hp[k] == kUnpublished) hp[k] = peek(rj + 2 * g + 1);
     }
   }
   v = -1.0;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       s_wp[wave] = bp;
     }
     __syncthreads();
-    const double* rj = a.rec + (int64_t)j * a.nwg * a.rs;
+    double* rj = a.rec + (int64_t)j * a.nwg * a.rs;   // this step's area
     bool ok = true;
     if (wave == 0) {
       // ---- the workgroup's best column and its reflector, published --------
@@ -168,23 +169,24 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       int p = (lane < kSqWaves) ? s_wp[lane] : INT_MAX;
       int w = lane;
       row0_argmax(v, p, w);
-      double* rec = a.rec + ((int64_t)j * a.nwg + wg) * a.rs;
+      double* head = rj + 2 * wg;
+      double* body = rj + 2 * a.nwg + (int64_t)wg * (a.rs - 2);
       if (lane == 0) {
-        publish(rec, v);
-        publish(rec + 1, (double)p);
+        publish(head, v);
+        publish(head + 1, (double)p);
       }
       double beta = 0.0, scale = 0.0, tau = 0.0;
       if (p != INT_MAX) {
         // v is the sum of squares of the column's rows j.., the s2 of its reflector
         if (v > 0.0) reflector_coeffs(s_cand[w][j], v, beta, scale, tau);
         for (int r = lane; r < LM; r += 64)
-          publish(rec + kHead + r, (r < j) ? 0.0 : (r == j ? 1.0 : s_cand[w][r] * scale));
+          publish(body + 2 + r, (r < j) ? 0.0 : (r == j ? 1.0 : s_cand[w][r] * scale));
       } else {
-        for (int r = lane; r < LM; r += 64) publish(rec + kHead + r, 0.0);
+        for (int r = lane; r < LM; r += 64) publish(body + 2 + r, 0.0);
       }
       if (lane == 0) {
-        publish(rec + 2, tau);
-        publish(rec + 3, beta);
+        publish(body, tau);
+        publish(body + 1, beta);
       }
       // ---- the winner over all workgroups, from the record heads ----------
       double wv;
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       if (__builtin_amdgcn_ballot_w64(!ok) == 0 && wp != INT_MAX) {
         // fetch the winner's tau, beta and vector (words 2.. of its record)
         for (int r = 2 + lane; r < a.rs && ok; r += 64) {
-          const double* src = rj + (int64_t)ww * a.rs + r;
+          const double* src = rj + 2 * a.nwg + (int64_t)ww * (a.rs - 2) + (r - 2);
           unsigned long long bt = peek(src);
           uint32_t it = 0;
           while (bt == kUnpublished) {
@@ -285,26 +287,30 @@ int sq_lm(int ell) {
   return ((ell + 7) / 8) * 8;
 }
 
-// Records are packed (no padding) so that a step's records are polled as one
-// contiguous run of words.
+// A step's area holds nwg x (lm + 4) words: first the heads (norm^2, position)
+// of all workgroups, packed so that a poll of every head touches few cache
+// lines, then each workgroup's body (tau, beta, the lm-word vector).
 int sq_record_stride(int lm) { return lm + kHead; }
 
 // Every workgroup of the persistent kernel must be resident at once, so the
-// wider layout (8 lanes per column, twice the workgroups) is used only within
-// the caller's workgroup allowance.
+// workgroup count stays within the caller's allowance: 256-thread workgroups of
+// 64 columns (one wave per SIMD: the shortest step) when they fit, else
+// 512-thread workgroups of 128 columns, else 1024-thread ones of 256.
 int sq_groups(int64_t N, int max_groups) {
-  const int64_t g8 = (N + 127) / 128;
+  const int64_t g4 = (N + 63) / 64, g8 = (N + 127) / 128;
+  if (g4 <= max_groups) return (int)g4;
   return (int)(g8 <= max_groups ? g8 : (N + 255) / 256);
 }
 
-int sq_max_groups(int64_t N) { return (int)((N + 127) / 128); }
+int sq_max_groups(int64_t N) { return (int)((N + 63) / 64); }
 
 template <int LM>
 static hipError_t launch_lm(const SqArgs& a, hipStream_t s) {
   // the layout follows from the workgroup count chosen by sq_groups
-  const bool wide = (int64_t)a.nwg * 128 >= a.N;
   if (a.nwg < 1 || (int64_t)a.nwg * 256 < a.N) return hipErrorInvalidValue;
-  if (wide)
+  if ((int64_t)a.nwg * 64 >= a.N)
+    hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4, 256>), dim3(a.nwg), dim3(256), 0, s, a);
+  else if ((int64_t)a.nwg * 128 >= a.N)
     hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4, 512>), dim3(a.nwg), dim3(512), 0, s, a);
   else
     hipLaunchKernelGGL((sample_qrcp_kernel<LM, 4, 1024>), dim3(a.nwg), dim3(1024), 0, s, a);
