@@ -208,12 +208,19 @@ static int64_t panel_prep_words(int64_t M, int bj) {
   return hh + (bj >= 2 ? panel_cholqr_doubles(nwg) : 0);
 }
 
+// Buffers of the Cholesky-QR route after a panel's record words: Q (M x 64,
+// or ldq x 64 for an ldq up to the M the area is sized for), R = R2 R1,
+// L11^{-1} (64 x 64 each) and S (64).
+static int64_t panel_extra_doubles(int64_t M) { return M * 64 + 2 * 4096 + 64; }
+
 size_t panel_rec_doubles(int64_t M) {
-  return (size_t)(RQ_MAX_B + 1) * panel_groups(M) * 3 * 64 + (size_t)panel_cholqr_doubles(panel_groups(M));
+  return (size_t)(RQ_MAX_B + 1) * panel_groups(M) * 3 * 64 +
+         (size_t)panel_cholqr_doubles(panel_groups(M)) + (size_t)panel_extra_doubles(M);
 }
 
-rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
-                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt, bool prepared) {
+static PanelArgs panel_args(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
+                            double* tau, double* Y, int64_t ldy, double* T, int64_t ldt,
+                            int64_t ldq = 0) {
   PanelArgs a{};
   a.A = A;
   a.lda = lda;
@@ -233,6 +240,18 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
   const int64_t hh = (int64_t)(bj + 1) * a.nwg * 3 * 64;
   a.crec = bj >= 2 ? rec + hh : nullptr;
   a.fallback = a.crec ? h->sync + 2 : nullptr;
+  double* const extra = rec + panel_prep_words(M, bj);
+  a.ldq = std::max<int64_t>(ldq > 0 ? ldq : M, 1);   // ldq >= M; the area holds ldq x 64
+  a.qbuf = extra;
+  a.rbuf = extra + a.ldq * 64;
+  a.linv = a.rbuf + 4096;
+  a.sgnb = a.linv + 4096;
+  return a;
+}
+
+rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
+                    double* tau, double* Y, int64_t ldy, double* T, int64_t ldt, bool prepared) {
+  const PanelArgs a = panel_args(h, A, lda, M, bj, rec, tau, Y, ldy, T, ldt);
   if (!prepared) RQ_CHECK(h, launch_exchange_prep(h->sync, rec, panel_prep_words(M, bj), h->stream));
   KTimer kt(h, K_PANEL, 2.0 * (double)M * bj * bj, 8.0 * (double)M * (2.0 * bj + 64));
   RQ_CHECK(h, launch_panel(a, h->stream));
@@ -341,6 +360,8 @@ rq_status rq_destroy(rq_handle h) {
   }
   if (h->ev_z) (void)hipEventDestroy(h->ev_z);
   if (h->ev_u) (void)hipEventDestroy(h->ev_u);
+  if (h->ev_q) (void)hipEventDestroy(h->ev_q);
+  if (h->ev_p) (void)hipEventDestroy(h->ev_p);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->status) (void)hipFree(h->status);
@@ -667,6 +688,8 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     RQ_CHECK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_z, hipEventDisableTiming));
     RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_u, hipEventDisableTiming));
+    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_q, hipEventDisableTiming));
+    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_p, hipEventDisableTiming));
   }
   // The update of the rows below R12 runs on the side stream.  It is handed to
   // that stream only after the next block's sample QRCP is queued and waits on
@@ -725,13 +748,20 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     // into the caller's T when there is one: only its bj x bj block is touched)
     double* tj = T ? T + col0 * ldt : tblk;
     const int64_t ldtj = T ? ldt : 64;
-    RQ_TRY(run_panel(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tj, ldtj, true));
     const int64_t Nt = N - bj;
-    if (Nt <= 0) continue;
     double* Ctr = Ablk + bj * lda;                   // A(col0:, col0+bj:)
-    // 4. W = Y^T A_trailing (split-K partials), Z = T^T W
-    int ks, kc;
-    plan_split((int)M, (int)Nt, &ks, &kc);
+    const PanelArgs pa = panel_args(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tj, ldtj, m);
+    int ks = 1, kc = 64;
+    if (Nt > 0) plan_split((int)M, (int)Nt, &ks, &kc);
+    // The inner products of step 4 need only Q of the Cholesky-QR route
+    // (P = Q^T A_trailing; the reduce forms R12 = S P and Z from it), so they
+    // run on the side stream beside the panel's second half (the LU of Q11 - S
+    // and the reflectors).  The side stream's launch waits on an event
+    // recorded right before the second half's launch, which thus reaches the
+    // dispatcher first and gets its compute units.  When the column-by-column
+    // route runs instead, the same launch reads its Y (the panel's fallback
+    // flag selects the operand) and the reduce takes the W = Y^T A form.
+    const bool overlap = !resample && Nt > 0 && pa.crec && kc > 64;
     GemmArgs g{};
     g.L = ybuf;
     g.sLp = m;
@@ -748,19 +778,46 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     g.split_stride = (int64_t)64 * Nt;
     g.alpha = 1.0;
     g.beta = 0.0;
+    const double inner_flops = 2.0 * bj * (double)M * Nt;
+    const double inner_bytes = 8.0 * ((double)M * Nt + (double)M * bj + (double)ks * bj * Nt);
     {
-      KTimer kt(h, K_INNER, 2.0 * bj * (double)M * Nt,
-                8.0 * ((double)M * Nt + (double)M * bj + (double)ks * bj * Nt));
+      KTimer kt(h, K_PANEL, 2.0 * (double)M * bj * bj, 8.0 * (double)M * (2.0 * bj + 64));
+      RQ_CHECK(h, launch_panel_first(pa, s));
+    }
+    if (overlap) {
+      RQ_CHECK(h, hipEventRecord(h->ev_q, s));
+      RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_q, 0));
+      g.L = pa.qbuf;                                 // ldq = m, the strides of Y
+      g.L_alt = ybuf;
+      g.alt_if = pa.fallback;
+      {
+        KTimer kt(h, K_INNER, inner_flops, inner_bytes, h->side);
+        RQ_CHECK(h, launch_gemm_lx(g, h->side));
+      }
+      RQ_CHECK(h, hipEventRecord(h->ev_p, h->side));
+    }
+    {
+      KTimer kt(h, K_PANEL, 0.0, 0.0);
+      RQ_CHECK(h, launch_panel_second(pa, s));
+    }
+    if (Nt <= 0) continue;
+    // 4. W = Y^T A_trailing (split-K partials), Z = T^T W -- or, overlapped,
+    // P = Q^T A_trailing, R12 = S P, Z = L11^{-1} (A_top - S P)
+    if (overlap) {
+      RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_p, 0));
+    } else {
+      KTimer kt(h, K_INNER, inner_flops, inner_bytes);
       RQ_CHECK(h, launch_gemm_lx(g, s));
     }
     {
-      // with step 5 for rows 0..bj-1 (R12 -= Y11 Z): the sample update and the
-      // next block's sample QRCP need only them
+      // with step 5 for rows 0..bj-1 (R12): the sample update and the next
+      // block's sample QRCP need only them
       KTimer kt(h, K_REDUCE,
                 (double)bj * bj * Nt + (double)(ks - 1) * bj * Nt + 2.0 * bj * (double)bj * Nt,
                 8.0 * ((double)ks * bj * Nt + 64.0 * Nt + 2.0 * bj * (double)Nt));
       RQ_CHECK(h, launch_reduce_r12(part, g.split_stride, ks, (int)Nt, zbuf, tj, ldtj, ybuf, m,
-                                    Ctr, lda, bj, s));
+                                    Ctr, lda, bj, s, overlap ? pa.fallback : nullptr, pa.linv,
+                                    pa.sgnb));
     }
     if (resample) {
       // 5. A_trailing -= Y Z for the rows below R12, then 6'. the next sample,

@@ -227,6 +227,7 @@ __global__ __launch_bounds__(256, 1) void gemm_lx_ring_kernel(GemmArgs g) {
   const int kb = blockIdx.y * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
   const int first = kb + 16 * wave;               // this wave's groups: first + 64 i
+  const double* const Lb = (g.alt_if && *g.alt_if) ? g.L_alt : g.L;
   bool nok[NB];
   const double* xp[NB];
   const double* lp[PB];
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(256, 1) void gemm_lx_ring_kernel(GemmArgs g) {
   }
 #pragma unroll
   for (int i = 0; i < PB; ++i)
-    lp[i] = g.L + (int64_t)min(16 * i + l16, g.P - 1) * g.sLp + first + 4 * kq;
+    lp[i] = Lb + (int64_t)min(16 * i + l16, g.P - 1) * g.sLp + first + 4 * kq;
   dx4 acc[PB][NB];
 #pragma unroll
   for (int i = 0; i < PB; ++i)
@@ -386,6 +387,7 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
   const int pb = (g.P + 15) / 16;
   const bool lk1 = g.sLk == 1;
   if (g.skip_if && g.kchunk > 64) return hipErrorInvalidValue;   // only the narrow route skips
+  if (g.alt_if && !(lk1 && pb <= 4 && g.kchunk > 64)) return hipErrorInvalidValue;   // ring route only
   if (lk1 && pb <= 4 && g.kchunk > 64) {
     dim3 grid((g.N + 31) / 32, g.ksplit);
     switch (pb) {
@@ -479,23 +481,35 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64
 }
 
 // reduce + R12 update of one block (steps 4 and 5 of Algorithm 4 for the rows
-// of R12): W(:, n) = sum_s part_s(:, n) in order s = 0, 1, ...; Z(:, n) =
-// T^T W(:, n) (rows bj..63 of Z zero); R12(:, n) -= Y11 Z(:, n), with Y11 the
-// leading bj x bj block of Y.  A workgroup takes 16 columns (4 per wave), so
-// that T and Y11 are staged in LDS once for all of them.
+// of R12).  A workgroup takes 16 columns (4 per wave), so that the 64 x 64
+// operands are staged in LDS once for all of them.  Two forms, chosen on the
+// device when `qflag` is given:
+//  * from W = Y^T A (qflag null, or *qflag != 0: the column-by-column panel
+//    ran): W(:, n) = sum_s part_s(:, n) in order s = 0, 1, ...; Z(:, n) =
+//    T^T W(:, n); R12(:, n) -= Y11 Z(:, n), with Y11 the leading bj x bj block
+//    of Y;
+//  * from P = Q^T A (*qflag == 0: the Cholesky-QR panel, whose Householder
+//    block has first b columns Q S and Y11 = L11): P(:, n) = sum_s part_s(:, n);
+//    R12(:, n) = S P(:, n), and as R12 = A_top - Y11 Z, Z(:, n) =
+//    L11^{-1} (A_top(:, n) - S P(:, n)), with A_top the rows of R12 before.
+// Rows bj..63 of Z are zero.
 __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, int64_t sstride,
                                                            int ks, int N, double* Z,
                                                            const double* T, int64_t ldt,
                                                            const double* Y, int64_t ldy,
-                                                           double* R12, int64_t ldr, int bj) {
-  __shared__ double s_T[64][65];   // s_T[q][i] = T(q, i), upper triangle
+                                                           double* R12, int64_t ldr, int bj,
+                                                           const uint32_t* qflag,
+                                                           const double* linv,
+                                                           const double* sgn) {
+  __shared__ double s_T[64][65];   // s_T[q][i] = T(q, i), upper triangle (or L^{-1}(i, q))
   __shared__ double s_Y[64][65];   // s_Y[r][i] = Y(r, i), r, i < bj
   __shared__ double s_v[4][64][4]; // per wave: the 4 columns' vectors, row-major [q][c]
   const int i = threadIdx.x & 63;
   const int cl = threadIdx.x >> 6;
+  const bool qr = qflag && *qflag == 0u;
   // wave cl takes the 4 columns 16 blockIdx + 4 cl + c together, so that every
-  // T and Y11 entry read from LDS feeds four products; their split-K partials
-  // and R12 entries are requested first, with the staging of T and Y11
+  // staged entry read from LDS feeds four products; their split-K partials
+  // and R12 entries are requested first, with the staging
   const int64_t n0 = (int64_t)blockIdx.x * 16 + 4 * cl;
   double w[4], r12[4];
 #pragma unroll
@@ -508,17 +522,27 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
     w[c] = acc;
     r12[c] = ok ? R12[i + n * ldr] : 0.0;
   }
+  if (qr) {
+    const double sg = (i < bj) ? sgn[i] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double rn = sg * w[c];    // R12 = S P
+      w[c] = r12[c] - rn;             // A_top - S P, the operand of L^{-1}
+      r12[c] = rn;
+    }
+  }
 #pragma unroll
   for (int e0 = 0; e0 < 64 * 64; e0 += 256) {
     const int e = e0 + threadIdx.x;
     const int a = e % 64, b = e / 64;
-    s_T[a][b] = (a < bj && b < bj && a <= b) ? T[a + (int64_t)b * ldt] : 0.0;
-    s_Y[a][b] = (a < bj && b < bj) ? Y[a + (int64_t)b * ldy] : 0.0;
+    const bool in = a < bj && b < bj && a <= b;
+    s_T[a][b] = in ? (qr ? linv[b * 64 + a] : T[a + (int64_t)b * ldt]) : 0.0;
+    if (!qr) s_Y[a][b] = (a < bj && b < bj) ? Y[a + (int64_t)b * ldy] : 0.0;
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) s_v[cl][i][c] = w[c];
   __syncthreads();
-  // Z(:, n) = T^T W(:, n)
+  // Z(:, n) = T^T W(:, n), or L^{-1} (A_top - S P)(:, n)
   double z[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
   for (int q = 0; q < 64; ++q) {
@@ -530,6 +554,12 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
   for (int c = 0; c < 4; ++c) {
     z[c] = (i < bj) ? z[c] : 0.0;
     if (n0 + c < N) Z[i + (n0 + c) * 64] = z[c];
+  }
+  if (qr) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (n0 + c < N && i < bj) R12[i + (n0 + c) * ldr] = r12[c];
+    return;
   }
   // the wave's own LDS accesses complete in order
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -555,11 +585,13 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
 
 hipError_t launch_reduce_r12(const double* part, int64_t sstride, int ks, int N, double* Z,
                              const double* T, int64_t ldt, const double* Y, int64_t ldy,
-                             double* R12, int64_t ldr, int bj, hipStream_t s) {
+                             double* R12, int64_t ldr, int bj, hipStream_t s,
+                             const uint32_t* qflag, const double* linv, const double* sgn) {
   if (N <= 0) return hipSuccess;
   if (bj < 1 || bj > 64) return hipErrorInvalidValue;
+  if (qflag && (!linv || !sgn)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reduce_t_r12_kernel, dim3((N + 15) / 16), dim3(256), 0, s, part, sstride, ks,
-                     N, Z, T, ldt, Y, ldy, R12, ldr, bj);
+                     N, Z, T, ldt, Y, ldy, R12, ldr, bj, qflag, linv, sgn);
   return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ struct rq_handle_s {
   int update_wgs = 256;        // compute units a trailing-update launch may fill (device count)
   int cus = 256;               // compute units of the device
   hipStream_t side = nullptr;  // second stream of the RQRCP block loop (created on first use)
-  hipEvent_t ev_z = nullptr, ev_u = nullptr;
+  hipEvent_t ev_z = nullptr, ev_u = nullptr, ev_q = nullptr, ev_p = nullptr;
   double* scratch = nullptr;   // device address of the static scratch array (rq_sample_qrcp_noalloc)
   std::string last_error;
   bool prof = false;

@@ -43,10 +43,22 @@ struct PanelArgs {
   int64_t ldy;
   double* T;           // out bj x bj upper triangular (zeros below), leading dim ldt
   int64_t ldt;
+  // Cholesky-QR route, between its two halves and for the Q-based products:
+  double* qbuf;        // M x 64 Q of the panel (leading dim ldq, zero beyond bj)
+  int64_t ldq;
+  double* rbuf;        // 64 x 64 R = R2 R1, row-major
+  double* linv;        // 64 x 64 L11^{-1} (unit lower, zero beyond bj), row-major
+  double* sgnb;        // [64] S (zero beyond bj)
 };
 constexpr int kPanelRows = 256;   // rows held by one workgroup
 // record words of the Cholesky-QR route of the panel for nwg workgroups
 inline int64_t panel_cholqr_doubles(int nwg) { return (int64_t)2 * nwg * 4096 + 2 * 4096 + 4096 + 64; }
+// The panel's kernels in order: launch_panel_first (the Cholesky-QR passes,
+// then the column-by-column route, which runs only when the first hands the
+// panel over), launch_panel_second (reconstruction and write-back of the
+// Cholesky-QR route; exits when the column route ran); launch_panel does both.
+hipError_t launch_panel_first(const PanelArgs& a, hipStream_t s);
+hipError_t launch_panel_second(const PanelArgs& a, hipStream_t s);
 hipError_t launch_panel(const PanelArgs& a, hipStream_t s);
 
 // ---- FP64 MFMA contraction D(P x N) = L(P x K) X(K x N) --------------------
@@ -60,6 +72,9 @@ struct GemmArgs {
   const double* C; int64_t ldc;
   const int64_t* xcol = nullptr;       // optional: column n of X is X + xcol[n] * ldx
   const int64_t* skip_if = nullptr;    // optional (K <= 64 only): no work when *skip_if != 0
+  // optional (P <= 64, unit k stride only): L_alt in place of L when *alt_if != 0
+  const double* L_alt = nullptr;
+  const uint32_t* alt_if = nullptr;
 };
 hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
 // split-K plan of launch_gemm_lx for P output rows (kchunk a multiple of 64)
@@ -92,9 +107,15 @@ hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float
 // leading dimension ldz = 64 (rows bj..63 zero) -- the trailing-update operand.
 // Fixed-order sum of ks split-K partials (ld 64) into W, Z = T^T W (64 x N, rows
 // bj.. zero) and R12(bj x N) -= Y11 Z, Y11 the leading bj x bj block of Y.
+// With qflag (the panel's fallback flag): when *qflag == 0 the partials are
+// those of P = Q^T A of the Cholesky-QR panel instead, and the kernel writes
+// R12 = S P and Z = L11^{-1} (R12_before - S P) (linv row-major, sgn as the
+// panel's second half leaves them).
 hipError_t launch_reduce_r12(const double* part, int64_t sstride, int ks, int N, double* Z,
                              const double* T, int64_t ldt, const double* Y, int64_t ldy,
-                             double* R12, int64_t ldr, int bj, hipStream_t s);
+                             double* R12, int64_t ldr, int bj, hipStream_t s,
+                             const uint32_t* qflag = nullptr, const double* linv = nullptr,
+                             const double* sgn = nullptr);
 hipError_t launch_reduce(const double* part, int64_t ldp, int64_t sstride, int ks, int P,
                          int N, double* out, int64_t ldout, const double* T, int64_t ldt,
                          int bj, hipStream_t s);

@@ -436,7 +436,10 @@ RQ_DEV bool gram_allreduce(const double* recs, double* red, double* G, double* s
   return !__syncthreads_or(!ok);
 }
 
-
+// First half of the Cholesky-QR route: the two passes give Q (written to
+// qbuf, all 64 columns) and workgroup 0 forms R = R2 R1 (to rbuf); the panel
+// itself is not written.  When a gate fails, the fallback flag hands the
+// untouched panel to the column-by-column route and the second half exits.
 __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a) {
   const int t = threadIdx.x;
   const int g = t % kPG;           // row group
@@ -450,8 +453,6 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
   // LDS: four 64 x 64 regions shared by the two routes, plus small vectors
   __shared__ double s_reg[4][kRegion];
   __shared__ double s_vec[5][kPC];
-  double* const s_tau = s_vec[0];
-  double (*const s_T)[kLd] = reinterpret_cast<double (*)[kLd]>(s_reg[1]);
 
   double x[kPR];
 #pragma unroll
@@ -467,14 +468,10 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
     double* const X = s_reg[2];
     double* const D = s_reg[3];
     double* const diag = s_vec[1];
-    double* const rcp = s_vec[2];
-    double* const sgn = s_vec[3];
-    double* const udiag = s_vec[4];
     double* const e1 = a.crec;                                   // [nwg][4096] Gram parts
     double* const e2 = e1 + (int64_t)a.nwg * kWords;             // [4096] Gram sum
     double* const e3 = e2 + kWords;                              // second pass
     double* const e4 = e3 + (int64_t)a.nwg * kWords;
-    double* const e5 = e4 + kWords;                              // [4096 + 64] U^{-1}, S
     // pass 1
     tile_gram(x, X, e1 + (int64_t)wg * kWords, t);
     if (!gram_allreduce(e1, e2, G, X, a.nwg, wg, t, a.abort_flag, a.status)) return;
@@ -565,33 +562,92 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
       }
       if (!ident) tile_times(x, X, D, t, rbase, 0);              // Q = Q1 R2^{-1}
       if (wg == 0) {
+        // R = R2 R1 (R2 upper: diag and G's lower part transposed), the 16 x 16
+        // block (bp, bq) per wave on the matrix cores; lane holds rows
+        // 16 bp + kq + 4 v, column 16 bq + l16
+        const int lane = t & 63, wave = t >> 6;
+        const int bp = wave >> 2, bq = wave & 3, l16 = lane & 15, kq = lane >> 4;
+        const int brow = 16 * bp + l16;                           // A-operand row of this lane
+        dx4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k0 = 0; k0 < kPC; k0 += 4) {
+          const int k = k0 + kq;
+          const double av = (brow < bj && k < bj && k >= brow)
+                                ? (k == brow ? diag[brow] : G[k * kLd + brow])
+                                : 0.0;
+          acc = mfma_f64(av, RB[k * kLd + 16 * bq + l16], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a.rbuf[(16 * bp + kq + 4 * v) * kPC + 16 * bq + l16] = acc[v];
+      }
+    }
+  }
+  // Q (all 64 columns: zero beyond bj) for the second half
+#pragma unroll
+  for (int i = 0; i < kPR; ++i) {
+    const int r = rbase + g + kPG * i;
+    if (r < a.M) a.qbuf[r + (int64_t)c * a.ldq] = x[i];
+  }
+}
+
+// Second half of the Cholesky-QR route (skipped when the first half handed
+// the panel to the column-by-column route): workgroup 0 factors Q11 - S = LU
+// without pivoting and publishes U^{-1} and S; then Y = (Q - [S; 0]) U^{-1}
+// (Y11 = L11), T = -U S L11^{-T}, the triangular factor S R, written back with
+// tau, and L11^{-1} and S for the inner products that use Q in place of Y.
+__global__ __launch_bounds__(kPanelThreads) void panel_cholqr_b_kernel(PanelArgs a) {
+  const int t = threadIdx.x;
+  const int g = t % kPG;           // row group
+  const int c = t / kPG;           // column
+  const int wg = blockIdx.x;
+  const int rbase = wg * kPanelRows;
+  const int bj = a.bj;
+  const bool colok = c < bj;
+  if (prior_timeout(a.status)) return;
+  if (*a.fallback) return;         // the column-by-column route factored the panel
+
+  __shared__ double s_reg[4][kRegion];
+  __shared__ double s_vec[5][kPC];
+  double* const s_tau = s_vec[0];
+  double (*const s_T)[kLd] = reinterpret_cast<double (*)[kLd]>(s_reg[1]);
+
+  double x[kPR];
+#pragma unroll
+  for (int i = 0; i < kPR; ++i) {
+    const int r = rbase + g + kPG * i;
+    x[i] = (r < a.M) ? a.qbuf[r + (int64_t)c * a.ldq] : 0.0;
+  }
+  {
+    double* const G = s_reg[0];
+    double* const RB = s_reg[1];
+    double* const X = s_reg[2];
+    double* const D = s_reg[3];
+    double* const rcp = s_vec[2];
+    double* const sgn = s_vec[3];
+    double* const udiag = s_vec[4];
+    double* const e5 = a.crec + 2 * ((int64_t)a.nwg * kWords + kWords);   // [4096 + 64] U^{-1}, S
+    {
+      if (wg == 0) {
         // the 16 x 16 block (bp, bq) of a 64 x 64 product per wave, on the
         // matrix cores; lane holds rows 16 bp + kq + 4 v, column 16 bq + l16
         const int lane = t & 63, wave = t >> 6;
         const int bp = wave >> 2, bq = wave & 3, l16 = lane & 15, kq = lane >> 4;
         const int brow = 16 * bp + l16;                           // A-operand row of this lane
-        // R = R2 R1 into D (R2 upper: diag and G's lower part transposed)
-        {
-          dx4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int k0 = 0; k0 < kPC; k0 += 4) {
-            const int k = k0 + kq;
-            const double av = (brow < bj && k < bj && k >= brow)
-                                  ? (k == brow ? diag[brow] : G[k * kLd + brow])
-                                  : 0.0;
-            acc = mfma_f64(av, RB[k * kLd + 16 * bq + l16], acc);
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) D[(16 * bp + kq + 4 * v) * kLd + 16 * bq + l16] = acc[v];
-        }
-        __syncthreads();                                         // G (R2) is overwritten next
-        // Q11 into G, then its signed LU with U^{-1} in X and L^{-1} in RB
+        // R = R2 R1 from the first half, and Q11 into G; then its signed LU
+        // with U^{-1} in X and L^{-1} in RB
+        for (int e = t; e < kWords; e += kPanelThreads) D[(e >> 6) * kLd + (e & 63)] = a.rbuf[e];
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) G[(g + 16 * ii) * kLd + c] = x[ii];
         __syncthreads();
         lu_signed(G, X, RB, sgn, udiag, rcp, bj, t);
         for (int e = t; e < kWords; e += kPanelThreads) publish(e5 + e, X[(e >> 6) * kLd + (e & 63)]);
         if (t < kPC) publish(e5 + kWords + t, t < bj ? sgn[t] : 0.0);
+        // L^{-1} (unit lower, zero beyond bj) and S for the inner products
+        for (int e = t; e < kWords; e += kPanelThreads) {
+          const int i = e >> 6, q = e & 63;
+          a.linv[e] = (i < bj && q < bj) ? RB[i * kLd + q] : 0.0;
+        }
+        if (t < kPC) a.sgnb[t] = t < bj ? sgn[t] : 0.0;
         // T = -U S L^{-T}: T[i][j] = -sum_{k=i..j} U[i][k] S[k] W[j][k]
         // (U: udiag and G's strict upper part; W = L^{-1} in RB, read transposed)
         dx4 tacc = {0.0, 0.0, 0.0, 0.0};
@@ -868,7 +924,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(PanelArgs a) {
 }
 
 
-hipError_t launch_panel(const PanelArgs& a, hipStream_t s) {
+hipError_t launch_panel_first(const PanelArgs& a, hipStream_t s) {
   if (a.crec) {
     hipLaunchKernelGGL(panel_cholqr_kernel, dim3(a.nwg), dim3(kPanelThreads), 0, s, a);
     const hipError_t e = hipGetLastError();
@@ -876,6 +932,17 @@ hipError_t launch_panel(const PanelArgs& a, hipStream_t s) {
   }
   hipLaunchKernelGGL(panel_kernel, dim3(a.nwg), dim3(kPanelThreads), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_panel_second(const PanelArgs& a, hipStream_t s) {
+  if (!a.crec) return hipSuccess;
+  hipLaunchKernelGGL(panel_cholqr_b_kernel, dim3(a.nwg), dim3(kPanelThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_panel(const PanelArgs& a, hipStream_t s) {
+  const hipError_t e = launch_panel_first(a, s);
+  return e != hipSuccess ? e : launch_panel_second(a, s);
 }
 
 }  // namespace rq
