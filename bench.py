@@ -890,10 +890,10 @@ def bench_serve_c5(args):
 
 # name, m, n, spectrum (kind, parameter, floor)
 QUALITY_MATRICES = (
-    ("ex33_like_1733", 1733, 1733, ("pow10", 3.0 / 1733.0, 0.0)),
-    ("lock2232_like_2232", 2232, 2232, ("poly", 1.0, 0.0)),
-    ("gear_like_2442x3888", 2442, 3888, ("poly", 1.5, 1e-3)),
-    ("lpi_gran_like_2658x2525", 2658, 2525, ("exp", 100.0, 1e-6)),
+    ("smooth_1733x1733_pow10", 1733, 1733, ("pow10", 3.0 / 1733.0, 0.0)),
+    ("smooth_2232x2232_poly1", 2232, 2232, ("poly", 1.0, 0.0)),
+    ("smooth_2442x3888_poly1.5", 2442, 3888, ("poly", 1.5, 1e-3)),
+    ("smooth_2658x2525_exp100", 2658, 2525, ("exp", 100.0, 1e-6)),
 )
 
 
