@@ -22,6 +22,8 @@
 // Work that is the same for the whole workgroup (its record, the winner) is
 // done by wave 0 alone: with several waves per SIMD, repeating it in every
 // wave would cost several times its latency on every step.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "rqrcp.h"
@@ -297,6 +299,8 @@ int sq_record_stride(int lm) { return lm + kHead; }
 // 64 columns (one wave per SIMD: the shortest step) when they fit, else
 // 512-thread workgroups of 128 columns, else 1024-thread ones of 256.
 int sq_groups(int64_t N, int max_groups) {
+  // wave 0 polls at most kHeadPer heads per lane
+  max_groups = std::min(max_groups, kHeadPer * 64);
   const int64_t g4 = (N + 63) / 64, g8 = (N + 127) / 128;
   if (g4 <= max_groups) return (int)g4;
   return (int)(g8 <= max_groups ? g8 : (N + 255) / 256);
