@@ -375,6 +375,32 @@ void plan_split_target(int K, int N, int cols, int target, int* ksplit, int* kch
   *kchunk = kc;
 }
 
+// Split for the ring kernel (P <= 64) by resident rounds: with `slots`
+// workgroups resident at once, the ks (at most 8) that minimizes the rounds
+// times the rows each workgroup streams, plus a fixed cost of 320 rows per
+// workgroup (its start and the combination of its waves).  Ties keep the
+// smaller ks (fewer partials to reduce).
+void plan_split_rounds(int K, int N, int slots, int* ksplit, int* kchunk) {
+  const int tiles = (N + 31) / 32;
+  const int kmax = std::max(1, std::min((K + 255) / 256, 8));
+  int best_ks = 1, best_kc = std::max(64, ((K + 63) / 64) * 64);
+  int64_t best = -1;
+  for (int ks = 1; ks <= kmax; ++ks) {
+    int kc = (K + ks - 1) / ks;
+    kc = std::max(64, ((kc + 63) / 64) * 64);
+    const int ks2 = (K + kc - 1) / kc;
+    const int64_t rounds = ((int64_t)tiles * ks2 + slots - 1) / slots;
+    const int64_t cost = rounds * (kc + 320);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_ks = ks2;
+      best_kc = kc;
+    }
+  }
+  *ksplit = best_ks;
+  *kchunk = best_kc;
+}
+
 // FP64 gemm_lx: 32 output columns per workgroup; one workgroup per CU for the
 // ring kernel (P <= 64), two for the general kernel.
 void plan_split(int K, int N, int* ksplit, int* kchunk, int P) {

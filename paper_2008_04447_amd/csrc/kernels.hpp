@@ -80,6 +80,8 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s);
 // split-K plan of launch_gemm_lx for P output rows (kchunk a multiple of 64)
 void plan_split(int K, int N, int* ksplit, int* kchunk, int P = 64);
 void plan_split_target(int K, int N, int cols, int target, int* ksplit, int* kchunk);
+// split of the ring route (P <= 64) by rounds of `slots` resident workgroups
+void plan_split_rounds(int K, int N, int slots, int* ksplit, int* kchunk);
 
 // ---- BF16 MFMA contractions (FP32 accumulate, FP64 results) -----------------
 struct GemmArgsF {
