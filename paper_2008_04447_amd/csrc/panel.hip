@@ -395,6 +395,33 @@ RQ_DEV void tile_times(double (&x)[kPR], double* X, const double* B, int t, int 
   }
 }
 
+// x <- x B as tile_times (keep_below = 0), with the product's chunks staged in
+// a second region Y (so each chunk needs two barriers instead of four) and the
+// Gram matrix of the result accumulated from them and published as record
+// words: the values and operation order of tile_times followed by tile_gram.
+RQ_DEV void tile_times_gram(double (&x)[kPR], double* X, double* Y, const double* B, double* rec,
+                            int t) {
+  const int g = t % kPG, c = t / kPG, lane = t & 63, wave = t >> 6;
+  const int p = wave >> 2, q = wave & 3;
+  dx4 gacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) X[(g + 16 * ii) * kLd + c] = x[4 * ch + ii];
+    __syncthreads();   // X complete; every wave is done with Y of the previous chunk
+    const dx4 acc = product_chunk(X, B, p, q, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Y[(16 * p + (lane >> 4) + 4 * v) * kLd + 16 * q + (lane & 15)] = acc[v];
+    __syncthreads();   // Y complete; every wave is done with X
+    gacc = gram_chunk(Y, gacc, p, q, lane);
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) x[4 * ch + ii] = Y[(g + 16 * ii) * kLd + c];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    publish(rec + (16 * p + (lane >> 4) + 4 * v) * kPC + 16 * q + (lane & 15), gacc[v]);
+}
+
 // Gram matrix of this workgroup's tile, published as record words (row-major).
 RQ_DEV void tile_gram(const double (&x)[kPR], double* X, double* rec, int t) {
   const int g = t % kPG, c = t / kPG, lane = t & 63, wave = t >> 6;
@@ -493,9 +520,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_cholqr_kernel(PanelArgs a
         const int i = e >> 6, j = e & 63;
         RB[i * kLd + j] = (i < bj && j < bj) ? (i == j ? diag[i] : (j > i ? G[j * kLd + i] : 0.0)) : 0.0;
       }
-      tile_times(x, X, D, t, rbase, 0);                          // Q1 = X R1^{-1}
-      // pass 2
-      tile_gram(x, X, e3 + (int64_t)wg * kWords, t);
+      // Q1 = X R1^{-1} and, for pass 2, its Gram matrix (G is free: R1 is in RB)
+      tile_times_gram(x, X, G, D, e3 + (int64_t)wg * kWords, t);
       if (!gram_allreduce(e3, e4, G, X, a.nwg, wg, t, a.abort_flag, a.status)) return;
       // G = Q1^T Q1 = I + E, E of the order of kappa^2 eps.  With max |E| <= 1e-10
       // the factor and its inverse have closed forms to within rounding:
