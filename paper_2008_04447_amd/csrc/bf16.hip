@@ -183,7 +183,6 @@ hipError_t launch_gemm_lx_bf16(const GemmArgsF& g, hipStream_t s) {
 //   * Rows at or past M in the last tile are clamped to valid rows and their
 //     results dropped; columns past K (the K tail) are zero.
 // Products run in the same order as a plain k-ordered loop of 16x16x32 MFMAs.
-constexpr int kNnRows = 64;   // rows of C per workgroup
 constexpr int kNnK = 64;      // k per pipeline step
 constexpr int kNnLd = 72;     // LDS row stride of the BF16 Y tile (elements; 144 bytes)
 
@@ -209,30 +208,31 @@ __global__ void stage_z_bf16_kernel(const double* Z, int64_t ldz, int N, int K, 
   zt[e] = (__bf16)(float)((c < N && k < K) ? Z[k + (int64_t)c * ldz] : 0.0);
 }
 
-// The K loop of one workgroup.  VEC: Y 16-byte aligned, ldy and M multiples of 4
-// and ldy < 2^26 (32-bit lane offsets); otherwise element loads.
-template <int NBW, bool VEC>
-RQ_DEV void nn_tile(fx4 (&acc)[4][NBW], __bf16 (*s_y)[kNnRows * kNnLd], int M, const float* Y,
+// The K loop of one workgroup of 64 RB rows.  VEC: Y 16-byte aligned, ldy and
+// M multiples of 4 and ldy < 2^26 (32-bit lane offsets); otherwise element loads.
+template <int NBW, int RB, bool VEC>
+RQ_DEV void nn_tile(fx4 (&acc)[4 * RB][NBW], __bf16 (*s_y)[64 * RB * kNnLd], int M, const float* Y,
                     int64_t ldy, const __bf16* zt, int ncp, int K, int r0, int cw) {
+  constexpr int CPT = 4 * RB;           // columns of the step each loader thread reads
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int rg = t & 15, kc = t >> 4;   // loader: rows 4 rg .. 4 rg + 3, columns 4 kc .. 4 kc + 3
+  const int rg = t % (16 * RB), kc = t / (16 * RB);   // rows 4 rg .. 4 rg + 3, columns CPT kc ..
   // wave-uniform bases plus per-lane offsets
   const float* yw = Y + r0;
-  const uint32_t yoff = (uint32_t)min(4 * rg, M - 4 - r0) + (uint32_t)(4 * kc) * (uint32_t)ldy;
+  const uint32_t yoff = (uint32_t)min(4 * rg, M - 4 - r0) + (uint32_t)(CPT * kc) * (uint32_t)ldy;
   int64_t yoq[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) yoq[q] = min(4 * rg + q, M - 1 - r0) + (int64_t)(4 * kc) * ldy;
+  for (int q = 0; q < 4; ++q) yoq[q] = min(4 * rg + q, M - 1 - r0) + (int64_t)(CPT * kc) * ldy;
   const __bf16* zw = zt + (int64_t)cw * kNnK;
   const uint32_t zoff = (uint32_t)(l16 * kNnK + 8 * kq);
   const int nsteps = (K + kNnK - 1) / kNnK;
   const int nfull = K / kNnK;   // steps whose 64 columns are all below K
 
-  auto load_y = [&](fx4 (&u)[4], int s) {
+  auto load_y = [&](fx4 (&u)[CPT], int s) {
     const float* p = yw + (int64_t)(s * kNnK) * ldy;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < CPT; ++e) {
       const float* pe = p + (int64_t)e * ldy;
       if (VEC) {
         u[e] = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(pe + yoff));
@@ -242,12 +242,12 @@ RQ_DEV void nn_tile(fx4 (&acc)[4][NBW], __bf16 (*s_y)[kNnRows * kNnLd], int M, c
       }
     }
   };
-  auto load_y_tail = [&](fx4 (&u)[4], int s) {
+  auto load_y_tail = [&](fx4 (&u)[CPT], int s) {
     const int k0 = s * kNnK;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < CPT; ++e) {
       const float* pe = yw + (int64_t)(k0 + e) * ldy;
-      const bool ok = k0 + 4 * kc + e < K;
+      const bool ok = k0 + CPT * kc + e < K;
       if (VEC) {
         u[e] = ok ? *reinterpret_cast<const fx4*>(pe + yoff) : fx4{0.f, 0.f, 0.f, 0.f};
       } else {
@@ -259,33 +259,35 @@ RQ_DEV void nn_tile(fx4 (&acc)[4][NBW], __bf16 (*s_y)[kNnRows * kNnLd], int M, c
   auto zfrag = [&](int s, int h, int jb) {
     return *reinterpret_cast<const bf16x8*>((zw + ((int64_t)s * ncp + 16 * jb) * kNnK + 32 * h) + zoff);
   };
-  auto store_y = [&](__bf16* buf, const fx4 (&u)[4]) {
-    __bf16* p = buf + (4 * rg) * kNnLd + 4 * kc;
+  auto store_y = [&](__bf16* buf, const fx4 (&u)[CPT]) {
+    __bf16* p = buf + (4 * rg) * kNnLd + CPT * kc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<bf16x4*>(p + q * kNnLd) =
-          bf16x4{(__bf16)u[0][q], (__bf16)u[1][q], (__bf16)u[2][q], (__bf16)u[3][q]};
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int e0 = 0; e0 < CPT; e0 += 4)
+        *reinterpret_cast<bf16x4*>(p + q * kNnLd + e0) =
+            bf16x4{(__bf16)u[e0][q], (__bf16)u[e0 + 1][q], (__bf16)u[e0 + 2][q], (__bf16)u[e0 + 3][q]};
+    }
   };
   // MFMAs of one step from the LDS tile and the fragments in z; each half's
   // fragments are then replaced by those of step snext (always a valid step).
   auto compute = [&](const __bf16* buf, bf16x8 (&z)[2][NBW], int snext) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      bf16x8 yf[4];
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib)
-        yf[ib] = *reinterpret_cast<const bf16x8*>(buf + (16 * ib + l16) * kNnLd + 32 * h + 8 * kq);
+      for (int ib = 0; ib < 4 * RB; ++ib) {
+        const bf16x8 yf =
+            *reinterpret_cast<const bf16x8*>(buf + (16 * ib + l16) * kNnLd + 32 * h + 8 * kq);
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib)
-#pragma unroll
-        for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = mfma_bf16(z[h][jb], yf[ib], acc[ib][jb]);
+        for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = mfma_bf16(z[h][jb], yf, acc[ib][jb]);
+      }
 #pragma unroll
       for (int jb = 0; jb < NBW; ++jb) z[h][jb] = zfrag(snext, h, jb);
     }
   };
   if (nsteps == 0) return;
   const int last = nsteps - 1;
-  fx4 ya[4], yb[4];
+  fx4 ya[CPT], yb[CPT];
   bf16x8 z[2][NBW];
   auto load_z0 = [&]() {
 #pragma unroll
@@ -332,29 +334,29 @@ RQ_DEV void nn_tile(fx4 (&acc)[4][NBW], __bf16 (*s_y)[kNnRows * kNnLd], int M, c
   }
 }
 
-template <int NBW>
-__global__ __launch_bounds__(256, 2) void gemm_nn_bf16_kernel(double* C, int64_t ldc, int M, int N,
+template <int NBW, int RB>
+__global__ __launch_bounds__(256, 3 - RB) void gemm_nn_bf16_kernel(double* C, int64_t ldc, int M, int N,
                                                               const float* Y, int64_t ldy,
                                                               const __bf16* zt, int ncp, int K,
                                                               int vec) {
-  __shared__ __align__(16) __bf16 s_y[2][kNnRows * kNnLd];
+  __shared__ __align__(16) __bf16 s_y[2][64 * RB * kNnLd];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kq = lane >> 4;
-  const int r0 = blockIdx.x * kNnRows;
+  const int r0 = blockIdx.x * 64 * RB;
   const int cw = blockIdx.y * 64 * NBW + 16 * NBW * wave;
-  fx4 acc[4][NBW];
+  fx4 acc[4 * RB][NBW];
 #pragma unroll
-  for (int ib = 0; ib < 4; ++ib)
+  for (int ib = 0; ib < 4 * RB; ++ib)
 #pragma unroll
     for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = fx4{0.f, 0.f, 0.f, 0.f};
   if (vec)
-    nn_tile<NBW, true>(acc, s_y, M, Y, ldy, zt, ncp, K, r0, cw);
+    nn_tile<NBW, RB, true>(acc, s_y, M, Y, ldy, zt, ncp, K, r0, cw);
   else
-    nn_tile<NBW, false>(acc, s_y, M, Y, ldy, zt, ncp, K, r0, cw);
+    nn_tile<NBW, RB, false>(acc, s_y, M, Y, ldy, zt, ncp, K, r0, cw);
   // lane holds C(r0 + 16 ib + l16, cw + 16 jb + 4 kq + v)
 #pragma unroll
-  for (int ib = 0; ib < 4; ++ib) {
+  for (int ib = 0; ib < 4 * RB; ++ib) {
     const int r = r0 + 16 * ib + l16;
 #pragma unroll
     for (int jb = 0; jb < NBW; ++jb)
@@ -380,13 +382,28 @@ hipError_t launch_gemm_nn_bf16(double* C, int64_t ldc, int M, int N, const float
   }
   const int vec = (reinterpret_cast<uintptr_t>(Y) % 16 == 0) && (ldy % 4 == 0) && (M % 4 == 0) &&
                   ldy < (1 << 26);
-  dim3 grid((M + kNnRows - 1) / kNnRows, ncp / (64 * nbw));
-  switch (nbw) {
-    case 1: hipLaunchKernelGGL(gemm_nn_bf16_kernel<1>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
-    case 2: hipLaunchKernelGGL(gemm_nn_bf16_kernel<2>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
-    case 3: hipLaunchKernelGGL(gemm_nn_bf16_kernel<3>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
-    default: hipLaunchKernelGGL(gemm_nn_bf16_kernel<4>, grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec); break;
+  // 128 rows per workgroup when there are enough rows to fill the device that
+  // way (V, read by every workgroup, then costs half as much per row)
+  const int rb = ((int64_t)M >= 128 * 256) ? 2 : 1;
+  dim3 grid((M + 64 * rb - 1) / (64 * rb), ncp / (64 * nbw));
+#define RQ_NN(nbw_, rb_) \
+  hipLaunchKernelGGL((gemm_nn_bf16_kernel<nbw_, rb_>), grid, dim3(256), 0, s, C, ldc, M, N, Y, ldy, zbf, ncp, K, vec)
+  if (rb == 2) {
+    switch (nbw) {
+      case 1: RQ_NN(1, 2); break;
+      case 2: RQ_NN(2, 2); break;
+      case 3: RQ_NN(3, 2); break;
+      default: RQ_NN(4, 2); break;
+    }
+  } else {
+    switch (nbw) {
+      case 1: RQ_NN(1, 1); break;
+      case 2: RQ_NN(2, 1); break;
+      case 3: RQ_NN(3, 1); break;
+      default: RQ_NN(4, 1); break;
+    }
   }
+#undef RQ_NN
   return hipGetLastError();
 }
 
