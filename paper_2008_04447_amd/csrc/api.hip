@@ -585,6 +585,13 @@ rq_status rq_sample_qrcp_noalloc(rq_handle h, int64_t ell, int64_t n, int64_t st
 }  // extern "C"
 
 // Largest split-K buffer of any block of the RQRCP loop (and of the sketches).
+// Workgroup slots the inner products of a block of M rows plan their split of
+// K for: beside the panel's second half (the usual route) its workgroups hold
+// whole compute units, so they are left out.
+static int inner_slots(int64_t M, bool resample) {
+  return resample ? 256 : 256 - panel_groups(M);
+}
+
 static size_t rqrcp_part_doubles(int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,
                                  bool resample) {
   const int64_t ell = b + p;
@@ -593,7 +600,7 @@ static size_t rqrcp_part_doubles(int64_t m, int64_t n, int64_t k, int64_t b, int
     const int64_t nt = n - c0 - std::min<int64_t>(b, k - c0);
     if (nt <= 0) continue;
     int ks_b, kc_b;
-    plan_split_rounds((int)(m - c0), (int)nt, 256, &ks_b, &kc_b);
+    plan_split_rounds((int)(m - c0), (int)nt, inner_slots(m - c0, resample), &ks_b, &kc_b);
     w_part = std::max(w_part, (size_t)ks_b * 64 * nt);
     const int64_t c1 = c0 + std::min<int64_t>(b, k - c0);     // next block's sketch
     if (resample && c1 < k) w_part = std::max(w_part, sketch_part_doubles((int)ell, m - c1, n - c1));
@@ -752,7 +759,7 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     double* Ctr = Ablk + bj * lda;                   // A(col0:, col0+bj:)
     const PanelArgs pa = panel_args(h, Ablk, lda, M, bj, prec, tau + col0, ybuf, m, tj, ldtj, m);
     int ks = 1, kc = 64;
-    if (Nt > 0) plan_split_rounds((int)M, (int)Nt, 256, &ks, &kc);   // as sized in rqrcp_part_doubles
+    if (Nt > 0) plan_split_rounds((int)M, (int)Nt, inner_slots(M, resample), &ks, &kc);   // as sized in rqrcp_part_doubles
     // The inner products of step 4 need only Q of the Cholesky-QR route
     // (P = Q^T A_trailing; the reduce forms R12 = S P and Z from it), so they
     // run on the side stream beside the panel's second half (the LU of Q11 - S
