@@ -170,7 +170,7 @@ static int64_t panel_prep_words(int64_t M, int bj);
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm, hipEvent_t queued, double* panel_rec,
-                          int64_t panel_m, int panel_bj, int groups) {
+                          int64_t panel_m, int panel_bj, int groups, bool prepared) {
   const int lm = sq_lm(ell);
   SqArgs a{};
   a.B = B;
@@ -187,11 +187,13 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
   a.src_top = w.src_top;
   a.dst_low = w.dst_low;
   a.perm = perm;
-  if (panel_rec)
-    RQ_CHECK(h, launch_exchange_prep2(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, panel_rec,
-                                      panel_prep_words(panel_m, panel_bj), h->stream));
-  else
-    RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
+  if (!prepared) {
+    if (panel_rec)
+      RQ_CHECK(h, launch_exchange_prep2(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, panel_rec,
+                                        panel_prep_words(panel_m, panel_bj), h->stream));
+    else
+      RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
+  }
   KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
   if (queued) RQ_CHECK(h, hipEventRecord(queued, h->stream));
   RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
@@ -262,10 +264,10 @@ rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, doub
 // (columns bj..), B2 = S22 untouched (eq. update1).
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
                             const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat,
-                            const RankCheck* rk) {
+                            const RankCheck* rk, const RecordPrep* prep) {
   {
     KTimer kt(h, K_OMEGA11, (double)bj * bj * bj / 3.0, 8.0 * 2 * bj * bj);
-    RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, rk, h->stream));
+    RQ_CHECK(h, launch_omega11(sblk, ell, R11, ldr, bj, mhat, 64, rk, prep, h->stream));
   }
   GemmArgs u{};
   u.L = mhat;
@@ -731,6 +733,9 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
   RQ_TRY(sketch_fp64(h, (int)ell, m, n, Omega, ldo, A, lda, sample, ell, part));
   RQ_CHECK(h, launch_iota(jpvt, (int)n, s));
 
+  // the records of the next block's sample QRCP and panel were prepared by
+  // this block's sample-update launch
+  bool prepared = false;
   for (int64_t col0 = 0; col0 < k; col0 += b) {
     const int bj = (int)std::min<int64_t>(b, k - col0);
     const int64_t N = n - col0;
@@ -738,7 +743,8 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     double* Ablk = A + col0 + col0 * lda;            // trailing block A(col0:, col0:)
     // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
     RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr,
-                           side_queued ? h->ev_z : nullptr, prec, M, bj));
+                           side_queued ? h->ev_z : nullptr, prec, M, bj, /*groups=*/0, prepared));
+    prepared = false;
     if (side_queued) RQ_TRY(release_side(sq_groups(N, h->max_groups)));
     // the previous block's update of rows below its R12 must be complete
     if (pending_rows) {
@@ -866,8 +872,19 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
       rk.N = (int)Nt;
       rk.B = sample + (col0 + bj) * ell;
       rk.ldb = ell;
+      // the next block's records: its sample QRCP (bjn steps over Nn columns)
+      // and its panel (Mn rows), as run_sample_qrcp would prepare them
+      const int64_t col1 = col0 + bj;
+      const int bjn = (int)std::min<int64_t>(b, k - col1);
+      RecordPrep rp{};
+      rp.sync = h->sync;
+      rp.rec1 = sw.rec;
+      rp.n1 = (int64_t)bjn * sq_groups(n - col1, h->max_groups) * sq_record_stride(sq_lm((int)ell));
+      rp.rec2 = prec;
+      rp.n2 = panel_prep_words(m - col1, bjn);
       RQ_TRY(run_sample_update(h, sample + col0 * ell, (int)ell, Ablk, lda, Ctr, lda, bj, Nt,
-                               mhat, &rk));
+                               mhat, &rk, &rp));
+      prepared = true;
     }
     if (M > bj) {
       side = SideUpdate{Ctr + bj, M - bj, Nt, ybuf + bj, bj};

@@ -1048,11 +1048,29 @@ RQ_DEV void fresh_sample_tile(const RankCheck& rk, int tile) {
 // workgroup owns 16 columns of B: per chunk of 64 rows, thread t forms row t
 // of C - Y Z for those columns into LDS and stages column t of the Omega chunk,
 // then each thread accumulates ell / 4 rows of its column of B.
+//
+// Workgroups past those (nprep of them) set the next block's record areas to
+// the sentinel, which saves the launch of exchange_prep2 before its sample QRCP.
 __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t lds,
                                                      const double* R11, int64_t ldr, int bj,
-                                                     double* M, int64_t ldm, RankCheck rk) {
+                                                     double* M, int64_t ldm, RankCheck rk,
+                                                     RecordPrep rp, int nprep) {
   const int lane = threadIdx.x;
   const int i = blockIdx.x;
+  const int first_prep = (int)gridDim.x - nprep;
+  if (i >= first_prep) {
+    const int p = i - first_prep;
+    if (p == 0 && lane < 3) rp.sync[lane] = 0u;
+    unsigned long long* const r1 = reinterpret_cast<unsigned long long*>(rp.rec1);
+    unsigned long long* const r2 = reinterpret_cast<unsigned long long*>(rp.rec2);
+    for (int64_t e = (int64_t)p * 64 + lane; e < rp.n1 + rp.n2; e += (int64_t)nprep * 64) {
+      if (e < rp.n1)
+        r1[e] = kUnpublished;
+      else
+        r2[e - rp.n1] = kUnpublished;
+    }
+    return;
+  }
   if (rk.info) {
     bool resample = __hip_atomic_load(rk.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     if (!resample) {
@@ -1091,7 +1109,8 @@ __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t 
 }
 
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr, int bj,
-                          double* M, int64_t ldm, const RankCheck* rk, hipStream_t s) {
+                          double* M, int64_t ldm, const RankCheck* rk, const RecordPrep* prep,
+                          hipStream_t s) {
   if (bj < 1 || bj > 64) return hipErrorInvalidValue;
   RankCheck r{};
   int extra = 0;
@@ -1101,8 +1120,17 @@ hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int
       return hipErrorInvalidValue;
     extra = (r.N + kFreshCols - 1) / kFreshCols;
   }
-  hipLaunchKernelGGL(omega11_kernel, dim3(bj + extra), dim3(64), 0, s, S11, lds, R11, ldr, bj, M,
-                     ldm, r);
+  RecordPrep rp{};
+  int nprep = 0;
+  if (prep) {
+    rp = *prep;
+    if (!rp.sync || rp.n1 < 0 || rp.n2 < 0 || (rp.n1 > 0 && !rp.rec1) || (rp.n2 > 0 && !rp.rec2))
+      return hipErrorInvalidValue;
+    // about 32 words per thread, at least one workgroup (it clears the flags)
+    nprep = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (rp.n1 + rp.n2 + 2047) / 2048));
+  }
+  hipLaunchKernelGGL(omega11_kernel, dim3(bj + extra + nprep), dim3(64), 0, s, S11, lds, R11, ldr,
+                     bj, M, ldm, r, rp, nprep);
   return hipGetLastError();
 }
 

@@ -173,18 +173,22 @@ size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
 // that panel is then run with `prepared` set.  `groups` is the workgroup
 // allowance of the launch (0: the handle's max_groups, which leaves compute
 // units to the RQRCP side stream).
+// With `prepared`, the records (and the panel's, when panel_rec is given)
+// were prepared by an earlier launch (see launch_omega11) and no preparation
+// is launched here.
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
                           SqWork w, int64_t* perm, hipEvent_t queued = nullptr,
                           double* panel_rec = nullptr, int64_t panel_m = 0, int panel_bj = 0,
-                          int groups = 0);
+                          int groups = 0, bool prepared = false);
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,
                     double* tau, double* Y, int64_t ldy, double* T, int64_t ldt,
                     bool prepared = false);
 // With rk (RQRCP), the rank check of launch_omega11 runs in the same launch
-// and the product skips itself once rk->info is set.
+// and the product skips itself once rk->info is set; with prep, that launch
+// also prepares the next block's record areas.
 rq_status run_sample_update(rq_handle h, double* sblk, int ell, const double* R11, int64_t ldr,
                             const double* R12, int64_t ldr12, int bj, int64_t Nt, double* mhat,
-                            const RankCheck* rk = nullptr);
+                            const RankCheck* rk = nullptr, const RecordPrep* prep = nullptr);
 // Workspace bytes each entry point reserves for a problem shape (what
 // rq_workspace_query reports).
 size_t truncated_workspace_bytes(int64_t m, int64_t n, int64_t k, int ell, bool tuxv);

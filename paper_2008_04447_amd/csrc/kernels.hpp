@@ -182,10 +182,19 @@ struct RankCheck {
   int bj, ell, N;
   double* B; int64_t ldb;
 };
+// Record areas of the next block's exchanges, set to the sentinel (and the
+// handle's counter, abort and fallback words to zero) as exchange_prep2 does.
+struct RecordPrep {
+  uint32_t* sync;
+  double* rec1; int64_t n1;
+  double* rec2; int64_t n2;
+};
 // Omega_hat_11 = S11 R11^{-1} (bj x bj), S11 leading dim lds, R11 leading dim ldr;
-// with rk, the rank check above in the same launch.
+// with rk, the rank check above in the same launch; with prep, the record
+// areas it names are prepared by extra workgroups of the same launch.
 hipError_t launch_omega11(const double* S11, int64_t lds, const double* R11, int64_t ldr,
-                          int bj, double* M, int64_t ldm, const RankCheck* rk, hipStream_t s);
+                          int bj, double* M, int64_t ldm, const RankCheck* rk,
+                          const RecordPrep* prep, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 // dst[i] = (double)src[i] for i < n (contiguous arrays).
 hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
