@@ -1268,15 +1268,6 @@ hipError_t launch_exchange_prep2(uint32_t* sync, double* rec1, int64_t n1, doubl
   return hipGetLastError();
 }
 
-__global__ void zero_u32_kernel(uint32_t* v, int n) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) v[i] = 0u;
-}
-hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s) {
-  hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, v, n);
-  return hipGetLastError();
-}
-
 __global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,
                               int cols) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;

@@ -207,7 +207,6 @@ hipError_t launch_permute(double* X, int64_t ldx, int rows, int bj, int64_t ncol
                           const int* src_top, const int* dst_low, int64_t* jpvt, hipStream_t s);
 
 hipError_t launch_iota(int64_t* v, int n, hipStream_t s);
-hipError_t launch_zero_u32(uint32_t* v, int n, hipStream_t s);
 // Clears the barrier counter, abort flag and panel fallback flag (sync[0..2]) and marks the n record
 // words of a persistent kernel's exchange as unpublished.
 hipError_t launch_exchange_prep(uint32_t* sync, double* rec, int64_t n, hipStream_t s);
