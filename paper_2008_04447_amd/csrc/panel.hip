@@ -103,7 +103,9 @@ RQ_DEV bool wait_words(Src src, int total, Put put, int t, uint32_t* abort_flag,
 // kept past Minv's 64 rows.  Returns false when a pivot is not positive or not
 // finite (same value in all threads).
 RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
-  const int lane = t & 63, wave = t >> 6;
+  // the wave index as a scalar: the row indices derived from it select
+  // readlane sources directly (no readfirstlane before every broadcast)
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int g = t & 15, row = t >> 4;
   double* const rv = Minv + kPC * kLd;
   for (int e = t; e < kPC * kLd; e += kPanelThreads) Minv[e] = 0.0;
@@ -222,7 +224,7 @@ RQ_DEV bool chol_inv(double* A, double* Minv, double* diag, int n, int t) {
 // W[k][r] = -sum_{l=r}^{k-1} L[k][l] W[l][r].
 RQ_DEV void lu_signed(double* A, double* Z, double* W, double* sgn, double* udiag, double* rcp,
                         int n, int t) {
-  const int lane = t & 63, wave = t >> 6;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);   // scalar, as in chol_inv
   const int g = t & 15, row = t >> 4;
   for (int e = t; e < kPC * kLd; e += kPanelThreads) {
     Z[e] = 0.0;
