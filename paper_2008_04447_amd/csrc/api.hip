@@ -589,9 +589,10 @@ rq_status rq_sample_qrcp_noalloc(rq_handle h, int64_t ell, int64_t n, int64_t st
 // Largest split-K buffer of any block of the RQRCP loop (and of the sketches).
 // Workgroup slots the inner products of a block of M rows plan their split of
 // K for: beside the panel's second half (the usual route) its workgroups hold
-// whole compute units, so they are left out.
+// whole compute units, so they are left out -- down to a floor, since a panel
+// of up to 65536 rows can hold every unit (the product then mostly runs after it).
 static int inner_slots(int64_t M, bool resample) {
-  return resample ? 256 : 256 - panel_groups(M);
+  return resample ? 256 : std::max(64, 256 - panel_groups(M));
 }
 
 static size_t rqrcp_part_doubles(int64_t m, int64_t n, int64_t k, int64_t b, int64_t p,

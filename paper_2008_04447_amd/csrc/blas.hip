@@ -381,6 +381,7 @@ void plan_split_target(int K, int N, int cols, int target, int* ksplit, int* kch
 // workgroup (its start and the combination of its waves).  Ties keep the
 // smaller ks (fewer partials to reduce).
 void plan_split_rounds(int K, int N, int slots, int* ksplit, int* kchunk) {
+  slots = std::max(1, slots);
   const int tiles = (N + 31) / 32;
   const int kmax = std::max(1, std::min((K + 255) / 256, 8));
   int best_ks = 1, best_kc = std::max(64, ((K + 63) / 64) * 64);

@@ -173,6 +173,48 @@ def test_rqrcp_identity_compression_equals_qrcp(api):
     np.testing.assert_array_equal(jpvt, ref.jpvt)
 
 
+def _apply_q_inplace(qr, tau, x):
+    """H_1 ... H_k x for the reflectors stored in qr's lower part (unit diagonal)."""
+    x = np.array(x, dtype=np.float64)
+    for j in range(len(tau) - 1, -1, -1):
+        v = qr[j:, j].copy()
+        v[0] = 1.0
+        x[j:] -= tau[j] * np.outer(v, v @ x[j:])
+    return x
+
+
+def test_rqrcp_panel_holds_every_unit(api):
+    """65300 rows: the panel's 256 workgroups hold every compute unit, so the
+    inner products' split is planned for the floor of slots (regression: the
+    plan once divided by zero free slots)."""
+    from paper_2008_04447_amd._lib import RQError
+    m, n, b, p, k = 65300, 160, 64, 8, 160
+    a = synth.gaussian((m, n), 7101)
+    om = synth.omega(b + p, m, 7102)
+    try:
+        qr, jpvt, tau, _ = _rqrcp_case(api, m, n, b, p, k, a, om)
+    except RQError as e:
+        if e.code == 1003:   # RQ_E_UNSUPPORTED: fewer compute units than panel workgroups
+            pytest.skip("device has fewer than 256 compute units")
+        raise
+    ref = oracle.rqrcp(a, om, b, p, k=k)
+    pre = ref.trace.prefix(ref.sample_scale, REL, ABS)
+    assert pre >= 64, f"certified prefix only {pre}"
+    assert sorted(jpvt) == list(range(n))
+    np.testing.assert_array_equal(jpvt[:pre], ref.jpvt[:pre])
+    floor = 1e-12 * np.linalg.norm(a)
+    d = np.linalg.norm(np.triu(qr[:pre]) - np.triu(ref.qr[:pre]), axis=1)
+    nrm = np.linalg.norm(np.triu(ref.qr[:pre]), axis=1)
+    assert np.all(d <= 1e-10 * nrm + floor)
+    # A P = Q R on 16 spread columns, through the stored reflectors (Q itself
+    # would be 65300^2)
+    cols = np.linspace(0, n - 1, 16).astype(int)
+    r = np.triu(qr[:n])[:, cols]
+    qrm = _apply_q_inplace(qr, tau, np.vstack([r, np.zeros((m - n, cols.size))]))
+    ap = a[:, jpvt[cols]]
+    assert np.linalg.norm(ap - qrm) / np.linalg.norm(ap) <= 1e-13
+
+
 def test_rqrcp_config_1000(api):
     """1000 x 1000, sigma_i = 10^(-i/100), b = 32, p = 8 (the parity workload)."""
     cfg = synth.workload(0)
