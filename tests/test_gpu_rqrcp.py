@@ -48,7 +48,11 @@ def test_sketch_matches_product(api, ell, m, n):
 
 
 # ----------------------------------------------------------------------------- sample QRCP
-@pytest.mark.parametrize("ell,n,steps", [(40, 1000, 32), (72, 8000, 64), (24, 257, 16), (8, 5, 5)])
+@pytest.mark.parametrize("ell,n,steps", [
+    (40, 1000, 32), (72, 8000, 64), (24, 257, 16), (8, 5, 5),
+    (72, 20000, 64),     # 256 columns per workgroup (1024 threads)
+    (72, 65536, 64),     # the widest sample: 256 such workgroups, one per compute unit
+])
 def test_sample_qrcp_matches_oracle(api, ell, n, steps):
     b = synth.gaussian((ell, n), 3000 + n) * (1.0 + np.arange(n) % 7)[None, :]
     B = _dev(api, b)
