@@ -168,8 +168,44 @@ size_t sq_rec_doubles(int ell, int64_t N) {
 static int panel_groups(int64_t M);
 static int64_t panel_prep_words(int64_t M, int bj);
 
+// Cross-stream ordering in the RQRCP block loop.  Each link (one direction of
+// one hand-over between the caller's stream and the side stream) has a 64-bit
+// word in the handle's sync area, zero since the handle was created, and a
+// running count on the host: the signalling stream writes the next count once
+// its earlier work has finished, and the waiting stream holds its later work
+// until the word has reached the count last written (stream memory
+// operations).  The waiting stream then goes on within about 3 us, where an
+// event wait took about 10.  A wait always names a count whose write is
+// already enqueued (the count only advances once its write is), so it cannot
+// wait forever.  A pending wait takes part of a compute unit while it polls,
+// which slows a persistent kernel that shares it: the side stream's waits,
+// pending across the sample QRCP and the panels, made both slower by more
+// than they saved, so those two links (Z, Q) use events, and the words carry
+// the caller's stream's waits (U, P), pending only between two kernels of
+// their own stream.  A call whose panels need every compute unit at once (a
+// 65300-row factorization on 256 units timed out with the words) uses events
+// throughout; h->link_values holds the choice for the current call.
+enum { kLinkZ = 0, kLinkU, kLinkQ, kLinkP };
+static bool link_on_words(rq_handle h, int l) {
+  return h->link_values && (l == kLinkU || l == kLinkP);
+}
+static uint64_t* link_word(rq_handle h, int l) {
+  return reinterpret_cast<uint64_t*>(h->sync + 32) + 4 * l;   // 32 bytes apart
+}
+static hipError_t link_signal(rq_handle h, int l, hipStream_t s) {
+  if (!link_on_words(h, l)) return hipEventRecord(h->link_ev[l], s);
+  const hipError_t e = hipStreamWriteValue64(s, link_word(h, l), h->link_count[l] + 1, 0);
+  if (e == hipSuccess) ++h->link_count[l];
+  return e;
+}
+static hipError_t link_wait(rq_handle h, int l, hipStream_t s) {
+  if (!link_on_words(h, l)) return hipStreamWaitEvent(s, h->link_ev[l], 0);
+  return hipStreamWaitValue64(s, link_word(h, l), h->link_count[l], hipStreamWaitValueGte,
+                              ~0ull);
+}
+
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
-                          SqWork w, int64_t* perm, hipEvent_t queued, double* panel_rec,
+                          SqWork w, int64_t* perm, bool signal_side, double* panel_rec,
                           int64_t panel_m, int panel_bj, int groups, bool prepared) {
   const int lm = sq_lm(ell);
   SqArgs a{};
@@ -195,7 +231,7 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
       RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
   }
   KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
-  if (queued) RQ_CHECK(h, hipEventRecord(queued, h->stream));
+  if (signal_side) RQ_CHECK(h, link_signal(h, kLinkZ, h->stream));
   RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
   return RQ_OK;
 }
@@ -360,10 +396,8 @@ rq_status rq_destroy(rq_handle h) {
     (void)hipStreamSynchronize(h->side);
     (void)hipStreamDestroy(h->side);
   }
-  if (h->ev_z) (void)hipEventDestroy(h->ev_z);
-  if (h->ev_u) (void)hipEventDestroy(h->ev_u);
-  if (h->ev_q) (void)hipEventDestroy(h->ev_q);
-  if (h->ev_p) (void)hipEventDestroy(h->ev_p);
+  for (hipEvent_t e : h->link_ev)
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->status) (void)hipFree(h->status);
@@ -696,14 +730,14 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
 
   if (!h->side) {
     RQ_CHECK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_z, hipEventDisableTiming));
-    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_u, hipEventDisableTiming));
-    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_q, hipEventDisableTiming));
-    RQ_CHECK(h, hipEventCreateWithFlags(&h->ev_p, hipEventDisableTiming));
+    for (hipEvent_t& e : h->link_ev) RQ_CHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+  // the panels, the widest persistent kernels of the loop, take panel_groups(m)
+  // compute units at most; a pending wait on the words may hold one more
+  h->link_values = panel_groups(m) < h->cus;
   // The update of the rows below R12 runs on the side stream.  It is handed to
   // that stream only after the next block's sample QRCP is queued and waits on
-  // an event recorded right before that launch: the persistent kernel needs
+  // a link signalled right before that launch: the persistent kernel needs
   // whole compute units, and reaching the dispatcher first it gets them before
   // the update's many workgroups fill the device.
   struct SideUpdate {
@@ -716,7 +750,7 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
   bool pending_rows = false;  // the side stream holds an update the main stream must wait for
   // `beside`: workgroups of the sample QRCP the update runs next to
   auto release_side = [&](int beside) -> rq_status {
-    RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_z, 0));
+    RQ_CHECK(h, link_wait(h, kLinkZ, h->side));
     {
       const double Mr = (double)side.M, Nr = (double)side.N;
       KTimer kt(h, K_UPDATE, 2.0 * side.bj * Mr * Nr,
@@ -724,7 +758,7 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
       RQ_CHECK(h, launch_update(side.C, lda, (int)side.M, (int)side.N, side.Y, m, zbuf, 64,
                                 side.bj, std::max(1, h->update_wgs - beside), h->side));
     }
-    RQ_CHECK(h, hipEventRecord(h->ev_u, h->side));
+    RQ_CHECK(h, link_signal(h, kLinkU, h->side));
     side_queued = false;
     pending_rows = true;
     return RQ_OK;
@@ -744,12 +778,12 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     double* Ablk = A + col0 + col0 * lda;            // trailing block A(col0:, col0:)
     // 1. sample pivots, QRCP(B, b); the sample is rewritten in pivoted order
     RQ_TRY(run_sample_qrcp(h, sample + col0 * ell, ell, (int)ell, N, bj, sw, nullptr,
-                           side_queued ? h->ev_z : nullptr, prec, M, bj, /*groups=*/0, prepared));
+                           side_queued, prec, M, bj, /*groups=*/0, prepared));
     prepared = false;
     if (side_queued) RQ_TRY(release_side(sq_groups(N, h->max_groups)));
     // the previous block's update of rows below its R12 must be complete
     if (pending_rows) {
-      RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
+      RQ_CHECK(h, link_wait(h, kLinkU, s));
       pending_rows = false;
     }
     // 2. permute all m rows of A's columns col0.. (finished R rows included), jpvt
@@ -770,8 +804,8 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     // The inner products of step 4 need only Q of the Cholesky-QR route
     // (P = Q^T A_trailing; the reduce forms R12 = S P and Z from it), so they
     // run on the side stream beside the panel's second half (the LU of Q11 - S
-    // and the reflectors).  The side stream's launch waits on an event
-    // recorded right before the second half's launch, which thus reaches the
+    // and the reflectors).  The side stream's launch waits on a link
+    // signalled right before the second half's launch, which thus reaches the
     // dispatcher first and gets its compute units.  When the column-by-column
     // route runs instead, the same launch reads its Y (the panel's fallback
     // flag selects the operand) and the reduce takes the W = Y^T A form.
@@ -799,8 +833,8 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
       RQ_CHECK(h, launch_panel_first(pa, s));
     }
     if (overlap) {
-      RQ_CHECK(h, hipEventRecord(h->ev_q, s));
-      RQ_CHECK(h, hipStreamWaitEvent(h->side, h->ev_q, 0));
+      RQ_CHECK(h, link_signal(h, kLinkQ, s));
+      RQ_CHECK(h, link_wait(h, kLinkQ, h->side));
       g.L = pa.qbuf;                                 // ldq = m, the strides of Y
       g.L_alt = ybuf;
       g.alt_if = pa.fallback;
@@ -808,7 +842,7 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
         KTimer kt(h, K_INNER, inner_flops, inner_bytes, h->side);
         RQ_CHECK(h, launch_gemm_lx(g, h->side));
       }
-      RQ_CHECK(h, hipEventRecord(h->ev_p, h->side));
+      RQ_CHECK(h, link_signal(h, kLinkP, h->side));
     }
     {
       KTimer kt(h, K_PANEL, 0.0, 0.0);
@@ -818,7 +852,7 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     // 4. W = Y^T A_trailing (split-K partials), Z = T^T W -- or, overlapped,
     // P = Q^T A_trailing, R12 = S P, Z = L11^{-1} (A_top - S P)
     if (overlap) {
-      RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_p, 0));
+      RQ_CHECK(h, link_wait(h, kLinkP, s));
     } else {
       KTimer kt(h, K_INNER, inner_flops, inner_bytes);
       RQ_CHECK(h, launch_gemm_lx(g, s));
@@ -893,10 +927,10 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     }
   }
   if (side_queued) {                // no sample QRCP follows: release it now
-    RQ_CHECK(h, hipEventRecord(h->ev_z, s));
+    RQ_CHECK(h, link_signal(h, kLinkZ, s));
     RQ_TRY(release_side(0));
   }
-  if (pending_rows) RQ_CHECK(h, hipStreamWaitEvent(s, h->ev_u, 0));
+  if (pending_rows) RQ_CHECK(h, link_wait(h, kLinkU, s));
   return RQ_OK;
 }
 

@@ -61,12 +61,17 @@ struct rq_handle_s {
   char* ws = nullptr;          // grow-only workspace
   size_t ws_bytes = 0;
   int64_t* status = nullptr;   // device int64[4]
-  uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag
+  uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag,
+                               // [2] panel fallback flag, [32..63] the block loop's stream links
   int max_groups = 128;        // workgroups one persistent sample-QRCP launch may use
   int update_wgs = 256;        // compute units a trailing-update launch may fill (device count)
   int cus = 256;               // compute units of the device
   hipStream_t side = nullptr;  // second stream of the RQRCP block loop (created on first use)
-  hipEvent_t ev_z = nullptr, ev_u = nullptr, ev_q = nullptr, ev_p = nullptr;
+  // the RQRCP block loop's links between its two streams: device words with
+  // the count each last had written, or events (see link_signal in api.hip)
+  uint64_t link_count[4] = {0, 0, 0, 0};
+  hipEvent_t link_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool link_values = true;     // the current call orders the streams through the words
   double* scratch = nullptr;   // device address of the static scratch array (rq_sample_qrcp_noalloc)
   std::string last_error;
   bool prof = false;
@@ -177,7 +182,7 @@ size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
 // were prepared by an earlier launch (see launch_omega11) and no preparation
 // is launched here.
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
-                          SqWork w, int64_t* perm, hipEvent_t queued = nullptr,
+                          SqWork w, int64_t* perm, bool signal_side = false,
                           double* panel_rec = nullptr, int64_t panel_m = 0, int panel_bj = 0,
                           int groups = 0, bool prepared = false);
 rq_status run_panel(rq_handle h, double* A, int64_t lda, int64_t M, int bj, double* rec,

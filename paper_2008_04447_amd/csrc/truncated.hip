@@ -124,7 +124,7 @@ static rq_status trqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64
     // 1. sample pivots (nothing runs beside them: the launch may take every
     //    compute unit the handle's launches may fill)
     RQ_TRY(run_sample_qrcp(h, w.sample + col0 * ell, ell, ell, N, bj, w.sw, /*perm=*/nullptr,
-                           /*queued=*/nullptr, /*panel_rec=*/nullptr, /*panel_m=*/0,
+                           /*signal_side=*/false, /*panel_rec=*/nullptr, /*panel_m=*/0,
                            /*panel_bj=*/0, /*groups=*/h->update_wgs));
     // 2. permute the index map, W^T and the finished R rows (A is not moved)
     {
