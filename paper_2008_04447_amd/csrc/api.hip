@@ -178,17 +178,19 @@ static int64_t panel_prep_words(int64_t M, int bj);
 // event wait took about 10.  A wait always names a count whose write is
 // already enqueued (the count only advances once its write is), so it cannot
 // wait forever.  A pending wait takes part of a compute unit while it polls,
-// which slows a persistent kernel that shares it: the side stream's waits,
-// pending across the sample QRCP and the panels, made both slower by more
-// than they saved, so those two links (Z, Q) use events, and the words carry
-// the caller's stream's waits (U, P), pending only between two kernels of
-// their own stream.  A call whose panels need every compute unit at once (a
-// 65300-row factorization on 256 units timed out with the words) uses events
+// which slows a persistent kernel that shares it.  The words carry the caller's
+// stream's waits (U, P), pending only between two kernels of their own stream,
+// and the update's release (Z), which the sample QRCP kernel itself writes
+// once all its workgroups hold their compute units: the side stream's wait for
+// it polls beside the panel's second half and the short kernels that follow,
+// and the caller's stream needs no operation before the sample QRCP.  The
+// product's start (Q) stays on an event: a wait for it would poll across the
+// sample QRCP and the first panel half, and slowed both by more than it saved.
+// A call whose panels need every compute unit at once (a 65300-row
+// factorization on 256 units timed out with the words) uses events
 // throughout; h->link_values holds the choice for the current call.
 enum { kLinkZ = 0, kLinkU, kLinkQ, kLinkP };
-static bool link_on_words(rq_handle h, int l) {
-  return h->link_values && (l == kLinkU || l == kLinkP);
-}
+static bool link_on_words(rq_handle h, int l) { return h->link_values && l != kLinkQ; }
 static uint64_t* link_word(rq_handle h, int l) {
   return reinterpret_cast<uint64_t*>(h->sync + 32) + 4 * l;   // 32 bytes apart
 }
@@ -231,8 +233,16 @@ rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t 
       RQ_CHECK(h, launch_exchange_prep(h->sync, w.rec, (int64_t)steps * a.nwg * a.rs, h->stream));
   }
   KTimer kt(h, K_SAMPLE_QRCP, 6.0 * ell * (double)N * steps, 16.0 * ell * (double)N);
-  if (signal_side) RQ_CHECK(h, link_signal(h, kLinkZ, h->stream));
+  if (signal_side) {
+    if (link_on_words(h, kLinkZ)) {   // the kernel writes the word
+      a.release = link_word(h, kLinkZ);
+      a.release_value = h->link_count[kLinkZ] + 1;
+    } else {
+      RQ_CHECK(h, link_signal(h, kLinkZ, h->stream));
+    }
+  }
   RQ_CHECK(h, launch_sample_qrcp(a, lm, h->stream));
+  if (a.release) ++h->link_count[kLinkZ];
   return RQ_OK;
 }
 

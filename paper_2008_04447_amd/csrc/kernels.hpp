@@ -18,6 +18,8 @@ struct SqArgs {
   int* src_top;        // [steps]: input position of the column ending at q < steps
   int* dst_low;        // [steps]: final position of input column o < steps (or -1 if < steps)
   int64_t* perm;       // [N] or null: perm[final] = input position
+  uint64_t* release;   // or null: set to release_value once every workgroup is resident
+  uint64_t release_value;   // (after the first exchange), and on every way out
 };
 int sq_lm(int ell);    // padded register height used for a given ell (0 = unsupported)
 int sq_record_stride(int lm);

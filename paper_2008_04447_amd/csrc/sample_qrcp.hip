@@ -96,8 +96,16 @@ RQ_DEV bool poll_winner(const double* rj, const SqArgs& a, int lane, double& v, 
   return ok;
 }
 
+// The release word (optional) tells a stream waiting on it that every
+// workgroup holds its compute unit: workgroup 0 sets it once the first step's
+// heads are all in, and again on its way out, so that a wait on it ends
+// whatever path the kernel takes.
+RQ_DEV void sq_release(const SqArgs& a) {
+  __hip_atomic_store(a.release, a.release_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int LM, int Q, int NT>
-__global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
+RQ_DEV void sample_qrcp_body(const SqArgs& a) {
   constexpr int kQ = Q;                        // lanes per column
   constexpr int kSqCols = NT / kQ;             // columns per workgroup
   constexpr int kSqWaves = SqShape<NT>::kWaves;
@@ -194,6 +202,7 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       double wv;
       int wp, ww;
       ok = poll_winner(rj, a, lane, wv, wp, ww);
+      if (j == 0 && wg == 0 && lane == 0 && ok && a.release) sq_release(a);
       if (__builtin_amdgcn_ballot_w64(!ok) == 0 && wp != INT_MAX) {
         // fetch the winner's tau, beta and vector (words 2.. of its record)
         for (int r = 2 + lane; r < a.rs && ok; r += 64) {
@@ -282,6 +291,12 @@ __global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
       if (a.perm) a.perm[pos] = c;
     }
   }
+}
+
+template <int LM, int Q, int NT>
+__global__ __launch_bounds__(NT) void sample_qrcp_kernel(SqArgs a) {
+  sample_qrcp_body<LM, Q, NT>(a);
+  if (a.release && blockIdx.x == 0 && threadIdx.x == 0) sq_release(a);
 }
 
 int sq_lm(int ell) {
