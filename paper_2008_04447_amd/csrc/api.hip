@@ -740,7 +740,8 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
 
   if (!h->side) {
     RQ_CHECK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-    for (hipEvent_t& e : h->link_ev) RQ_CHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipEvent_t& e : h->link_ev)
+      RQ_CHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
   }
   // the panels, the widest persistent kernels of the loop, take panel_groups(m)
   // compute units at most; a pending wait on the words may hold one more
