@@ -190,9 +190,55 @@ static int64_t panel_prep_words(int64_t M, int bj);
 // which takes a hand-over from about 10 to about 7 us.
 // A call whose panels need every compute unit at once (a 65300-row
 // factorization on 256 units timed out with the words) uses events
-// throughout; h->link_values holds the choice for the current call.
+// throughout, and so does every call where kernels of two streams do not run
+// at the same time (a profiler's counter collection, kernel serialization):
+// there a word wait, itself a kernel, would wait for a kernel that cannot
+// start.  h->link_values holds the choice for the current call.
 enum { kLinkZ = 0, kLinkU, kLinkQ, kLinkP };
 static bool link_on_words(rq_handle h, int l) { return h->link_values && l != kLinkQ; }
+// Each of two one-wave kernels, one per stream, sets its own flag and waits
+// (at most `ticks` of the wall clock) for the other's: both see each other only
+// when the two streams' kernels run at the same time.  words: u32[4], zero
+// before; [0], [1] the flags, [2], [3] what each kernel saw.
+__global__ void concurrency_probe_kernel(uint32_t* words, int me, uint64_t ticks) {
+  if (threadIdx.x != 0) return;
+  __hip_atomic_store(words + me, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t0 = wall_clock64();
+  uint32_t seen = 0u;
+  while (wall_clock64() - t0 < ticks) {
+    if (__hip_atomic_load(words + (1 - me), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      seen = 1u;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __hip_atomic_store(words + 2 + me, seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Run once per handle, on the side stream and a stream of its own (never the
+// caller's, whose queued work it does not wait for); blocks the host for the
+// two kernels only, about 2 ms at most each.
+static bool streams_run_concurrently(rq_handle h) {
+  uint32_t* w = h->sync + 8;     // zero since the handle was created
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess ||
+      khz <= 0)
+    return false;
+  const uint64_t ticks = 2ull * (uint64_t)khz;   // 2 ms
+  hipStream_t other = nullptr;
+  if (hipStreamCreateWithFlags(&other, hipStreamNonBlocking) != hipSuccess) return false;
+  hipLaunchKernelGGL(concurrency_probe_kernel, dim3(1), dim3(64), 0, h->side, w, 0, ticks);
+  hipLaunchKernelGGL(concurrency_probe_kernel, dim3(1), dim3(64), 0, other, w, 1, ticks);
+  bool ok = hipGetLastError() == hipSuccess;
+  ok = (hipStreamSynchronize(other) == hipSuccess) && ok;
+  (void)hipStreamDestroy(other);
+  uint32_t seen[2] = {0u, 0u};
+  ok = ok && hipMemcpyAsync(seen, w + 2, sizeof(seen), hipMemcpyDeviceToHost, h->side) == hipSuccess;
+  ok = (hipStreamSynchronize(h->side) == hipSuccess) && ok;
+  (void)hipGetLastError();
+  return ok && seen[0] == 1u && seen[1] == 1u;
+}
+
 static uint64_t* link_word(rq_handle h, int l) {
   return reinterpret_cast<uint64_t*>(h->sync + 32) + 4 * l;   // 32 bytes apart
 }
@@ -744,10 +790,11 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
     RQ_CHECK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     for (hipEvent_t& e : h->link_ev)
       RQ_CHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
+    h->words_ok = streams_run_concurrently(h);
   }
   // the panels, the widest persistent kernels of the loop, take panel_groups(m)
   // compute units at most; a pending wait on the words may hold one more
-  h->link_values = panel_groups(m) < h->cus;
+  h->link_values = h->words_ok && panel_groups(m) < h->cus;
   // The update of the rows below R12 runs on the side stream.  It is handed to
   // that stream only after the next block's sample QRCP is queued and waits on
   // a link signalled right before that launch: the persistent kernel needs

@@ -62,7 +62,8 @@ struct rq_handle_s {
   size_t ws_bytes = 0;
   int64_t* status = nullptr;   // device int64[4]
   uint32_t* sync = nullptr;    // device u32[64]: [0] barrier counter, [1] abort flag,
-                               // [2] panel fallback flag, [32..63] the block loop's stream links
+                               // [2] panel fallback flag, [8..11] the concurrency probe,
+                               // [32..63] the block loop's stream links
   int max_groups = 128;        // workgroups one persistent sample-QRCP launch may use
   int update_wgs = 256;        // compute units a trailing-update launch may fill (device count)
   int cus = 256;               // compute units of the device
@@ -72,6 +73,7 @@ struct rq_handle_s {
   uint64_t link_count[4] = {0, 0, 0, 0};
   hipEvent_t link_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool link_values = true;     // the current call orders the streams through the words
+  bool words_ok = false;       // kernels of two streams were seen running at the same time
   double* scratch = nullptr;   // device address of the static scratch array (rq_sample_qrcp_noalloc)
   std::string last_error;
   bool prof = false;
