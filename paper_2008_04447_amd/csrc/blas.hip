@@ -463,6 +463,28 @@ hipError_t launch_gemm_lx(const GemmArgs& g, hipStream_t s) {
 // reduce: out(p, n) = sum_s part_s(p, n) in order s = 0, 1, ...; with T the
 // column is then multiplied by T^T (T upper triangular bj x bj):
 // Z(i, n) = sum_{q <= i} T(q, i) W(q, n), rows bj..63 of Z set to zero.
+// Split-K partials p[0], p[stride], ..., p[(ks - 1) stride] of one output:
+// the first eight are requested together (a loop with a run-time trip count
+// waited for each load before issuing the next); kSplitBatch values land in v.
+constexpr int kSplitBatch = 8;
+RQ_DEV void load_partials(const double* p, int64_t stride, int ks, bool ok,
+                          double (&v)[kSplitBatch]) {
+#pragma unroll
+  for (int r = 0; r < kSplitBatch; ++r) v[r] = (ok && r < ks) ? p[r * stride] : 0.0;
+}
+// Their sum in the order s = 0, 1, ... (starting from the first partial, not
+// from 0.0 + it: that add was folded into the first load's branch, with a
+// wait for it before the other loads).
+RQ_DEV double sum_partials(const double* p, int64_t stride, int ks, bool ok,
+                           const double (&v)[kSplitBatch]) {
+  double acc = v[0];
+#pragma unroll
+  for (int r = 1; r < kSplitBatch; ++r)
+    if (r < ks) acc += v[r];
+  for (int r = kSplitBatch; ok && r < ks; ++r) acc += p[r * stride];
+  return acc;
+}
+
 __global__ __launch_bounds__(256) void reduce_plain_kernel(const double* part, int64_t ldp,
                                                            int64_t sstride, int ks, int P, int N,
                                                            double* out, int64_t ldout) {
@@ -470,9 +492,10 @@ __global__ __launch_bounds__(256) void reduce_plain_kernel(const double* part, i
   if (e >= (int64_t)P * N) return;
   const int p = (int)(e % P);
   const int64_t n = e / P;
-  double s = 0.0;
-  for (int q = 0; q < ks; ++q) s += part[q * sstride + p + n * ldp];
-  out[p + n * ldout] = s;
+  const double* src = part + p + n * ldp;
+  double v[kSplitBatch];
+  load_partials(src, sstride, ks, true, v);
+  out[p + n * ldout] = sum_partials(src, sstride, ks, true, v);
 }
 
 // Four columns per workgroup, one thread per (row i, column): the split-K
@@ -492,10 +515,11 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const double* part, int64
   const int i = threadIdx.x & 63;
   const int cl = threadIdx.x >> 6;
   const int64_t n = (int64_t)blockIdx.x * 4 + cl;
-  double w = 0.0;
-  if (n < N && i < bj)
-    for (int r = 0; r < ks; ++r) w += part[r * sstride + i + n * ldp];
-  s_w[cl][i] = w;
+  const bool ok = n < N && i < bj;
+  const double* src = part + i + (ok ? n : 0) * ldp;
+  double v[kSplitBatch];
+  load_partials(src, sstride, ks, ok, v);
+  s_w[cl][i] = sum_partials(src, sstride, ks, ok, v);
   __syncthreads();
   if (n >= N) return;
   double z = 0.0;
@@ -539,15 +563,19 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
   // and R12 entries are requested first, with the staging
   const int64_t n0 = (int64_t)blockIdx.x * 16 + 4 * cl;
   double w[4], r12[4];
+  double pv[4][kSplitBatch];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int64_t n = n0 + c;
     const bool ok = n < N && i < bj;
-    double acc = 0.0;
-    if (ok)
-      for (int r = 0; r < ks; ++r) acc += part[r * sstride + i + n * 64];
-    w[c] = acc;
+    load_partials(part + i + (ok ? n : 0) * 64, sstride, ks, ok, pv[c]);
     r12[c] = ok ? R12[i + n * ldr] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t n = n0 + c;
+    const bool ok = n < N && i < bj;
+    w[c] = sum_partials(part + i + (ok ? n : 0) * 64, sstride, ks, ok, pv[c]);
   }
   if (qr) {
     const double sg = (i < bj) ? sgn[i] : 0.0;
