@@ -158,6 +158,15 @@ rq_status rq_workspace_size(rq_handle h, size_t* bytes);
  *            update.  *info = 0 when the sample update was used throughout.
  *            A rank-deficient A thus factors with finite R and a valid
  *            permutation; it is a numerical warning, not an error.
+ * Streams: part of the work (the inner products beside the panel, the
+ * trailing update beside the next sample QRCP) runs on a second stream the
+ * handle owns, ordered against the handle's stream on the device; the
+ * handle's stream alone is what the caller synchronizes.  The first call on a
+ * handle creates that stream and blocks the host once, for at most about
+ * 4 ms, while two one-wave kernels on streams of the library's own (never the
+ * caller's) check that kernels of two streams run concurrently; where they do
+ * not (a profiler's counter collection, kernel serialization) the streams are
+ * ordered with events instead of device words.
  * Argument numbers for errors: h=1 m=2 n=3 k=4 b=5 p=6 A=7 lda=8 Omega=9
  * ldo=10 jpvt=11 tau=12 T=13 ldt=14 info=15.
  */
