@@ -19,8 +19,6 @@ namespace rq {
 // 16 k values (both operands use the same ordering of k).
 template <int PB>
 __global__ __launch_bounds__(256) void gemm_lx_narrow_kernel(GemmArgs g) {
-  if (g.skip_if && __hip_atomic_load(g.skip_if, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-    return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + wave * 16 + (lane & 15);
@@ -59,6 +57,10 @@ __global__ __launch_bounds__(256) void gemm_lx_narrow_kernel(GemmArgs g) {
       const int p = 16 * i + kq + 4 * v;
       cv[i][v] = (epi_c && p < g.P) ? g.C[p + (int64_t)n * g.ldc] : 0.0;
     }
+  // the skip flag is read after the operands are requested (they are in bounds
+  // either way), so its round trip overlaps theirs; nothing is stored before it
+  if (g.skip_if && __hip_atomic_load(g.skip_if, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+    return;
 #pragma unroll
   for (int c4 = 0; c4 < 4; ++c4) {
     if (kb + 16 * c4 >= ke) break;
@@ -557,7 +559,6 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
   __shared__ double s_v[4][64][4]; // per wave: the 4 columns' vectors, row-major [q][c]
   const int i = threadIdx.x & 63;
   const int cl = threadIdx.x >> 6;
-  const bool qr = qflag && *qflag == 0u;
   // wave cl takes the 4 columns 16 blockIdx + 4 cl + c together, so that every
   // staged entry read from LDS feeds four products; their split-K partials
   // and R12 entries are requested first, with the staging
@@ -577,6 +578,9 @@ __global__ __launch_bounds__(256) void reduce_t_r12_kernel(const double* part, i
     const bool ok = n < N && i < bj;
     w[c] = sum_partials(part + i + (ok ? n : 0) * 64, sstride, ks, ok, pv[c]);
   }
+  // the route flag is read after the partials are requested (they do not
+  // depend on it)
+  const bool qr = qflag && *qflag == 0u;
   if (qr) {
     const double sg = (i < bj) ? sgn[i] : 0.0;
 #pragma unroll
@@ -1100,11 +1104,22 @@ __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t 
     }
     return;
   }
+  // every load that does not depend on the rank check goes out first: R11's
+  // column of this lane (its diagonal entry among them), S11's entry and R_00
+  // (rows i >= bj, the fresh-sample tiles, skip the ones they never use)
+  const bool row = i < bj;
+  double rc[64];
+#pragma unroll
+  for (int q = 0; q < 64; ++q)
+    rc[q] = (row && lane < bj && q <= lane) ? R11[q + (int64_t)lane * ldr] : 0.0;
+  double sv = (row && lane < bj && lane >= i) ? S11[i + (int64_t)lane * lds] : 0.0;
+  const double diag = (lane < bj) ? R11[lane + (int64_t)lane * ldr] : 0.0;
   if (rk.info) {
     bool resample = __hip_atomic_load(rk.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const double r00 = *rk.r00;
     if (!resample) {
-      const double lim = rk.thresh * fabs(*rk.r00);
-      const bool small = lane < bj && fabs(R11[lane + (int64_t)lane * ldr]) <= lim;
+      const double lim = rk.thresh * fabs(r00);
+      const bool small = lane < bj && fabs(diag) <= lim;
       const unsigned long long hit = __builtin_amdgcn_ballot_w64(small);
       if (hit) {
         resample = true;
@@ -1113,18 +1128,13 @@ __global__ __launch_bounds__(64) void omega11_kernel(const double* S11, int64_t 
                              __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    if (i >= bj) {
+    if (!row) {
       if (resample) fresh_sample_tile(rk, i - bj);
       return;
     }
     if (resample) return;
   }
-  double rc[64];
-#pragma unroll
-  for (int q = 0; q < 64; ++q)
-    rc[q] = (lane < bj && q <= lane) ? R11[q + (int64_t)lane * ldr] : 0.0;
-  const double rinv = (lane < bj) ? 1.0 / R11[lane + (int64_t)lane * ldr] : 0.0;
-  double sv = (lane < bj && lane >= i) ? S11[i + (int64_t)lane * lds] : 0.0;
+  const double rinv = (lane < bj) ? 1.0 / diag : 0.0;
   double mine = 0.0;
 #pragma unroll
   for (int c = 0; c < 64; ++c) {
