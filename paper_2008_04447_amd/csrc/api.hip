@@ -7,6 +7,7 @@
 #include <cstring>
 #include <string>
 
+#include "device_common.hpp"
 #include "host.hpp"
 
 namespace rq {
@@ -171,31 +172,25 @@ static int64_t panel_prep_words(int64_t M, int bj);
 // Cross-stream ordering in the RQRCP block loop.  Each link (one direction of
 // one hand-over between the caller's stream and the side stream) has a 64-bit
 // word in the handle's sync area, zero since the handle was created, and a
-// running count on the host: the signalling stream writes the next count once
-// its earlier work has finished, and the waiting stream holds its later work
-// until the word has reached the count last written (stream memory
-// operations).  The waiting stream then goes on within about 3 us, where an
-// event wait took about 10.  A wait always names a count whose write is
-// already enqueued (the count only advances once its write is), so it cannot
-// wait forever.  A pending wait takes part of a compute unit while it polls,
-// which slows a persistent kernel that shares it.  The words carry the caller's
-// stream's waits (U, P), pending only between two kernels of their own stream,
-// and the update's release (Z), which the sample QRCP kernel itself writes
-// once all its workgroups hold their compute units: the side stream's wait for
-// it polls beside the panel's second half and the short kernels that follow,
-// and the caller's stream needs no operation before the sample QRCP.  The
-// product's start (Q) stays on an event: a wait for it would poll across the
-// sample QRCP and the first panel half, and slowed both by more than it saved.
-// The events skip the system-scope fence (both streams are on one device),
-// which takes a hand-over from about 10 to about 7 us.
-// A call whose panels need every compute unit at once (a 65300-row
-// factorization on 256 units timed out with the words) uses events
-// throughout, and so does every call where kernels of two streams do not run
-// at the same time (a profiler's counter collection, kernel serialization):
-// there a word wait, itself a kernel, would wait for a kernel that cannot
-// start.  h->link_values holds the choice for the current call.
+// running count on the host: the signalling side writes the next count once
+// its earlier work has finished, and the waiting stream runs a one-wave
+// kernel (wait_word_kernel) that holds its later work until the word has
+// reached the count last written; the hand-over then takes a few
+// microseconds, where an event took about 10 (7 without the system-scope
+// fence).  A wait always names a count whose write is already enqueued (the
+// count only advances once its write is), and the waiting kernel's spin is
+// bounded besides.  The writes: the side stream's work done (U, P) and the
+// product's start (Q) are stream memory operations; the update's release (Z)
+// is written by the sample QRCP kernel itself once all its workgroups hold
+// their compute units, so the caller's stream needs no operation before it.
+// A call whose panels need every compute unit at once uses events (a pending
+// wait holds part of a compute unit; a 65300-row factorization on 256 units
+// timed out with the words), and so does every call where kernels of two
+// streams do not run at the same time (a profiler's counter collection,
+// kernel serialization): there a waiting kernel would wait for a kernel that
+// cannot start.  h->link_values holds the choice for the current call.
 enum { kLinkZ = 0, kLinkU, kLinkQ, kLinkP };
-static bool link_on_words(rq_handle h, int l) { return h->link_values && l != kLinkQ; }
+static bool link_on_words(rq_handle h, int l) { return h->link_values; }
 // Each of two one-wave kernels, one per stream, sets its own flag and waits
 // (at most `ticks` of the wall clock) for the other's: both see each other only
 // when the two streams' kernels run at the same time.  words: u32[4], zero
@@ -248,10 +243,23 @@ static hipError_t link_signal(rq_handle h, int l, hipStream_t s) {
   if (e == hipSuccess) ++h->link_count[l];
   return e;
 }
+// Holds its stream until *word >= value: one wave that sleeps between its
+// polls (about one device-coherent load per microsecond), so a workgroup that
+// shares a compute unit with it loses few issue slots.  A wait that does not
+// end within the bounded spin sets the timeout bit and the abort flag.
+__global__ void wait_word_kernel(const uint64_t* word, uint64_t value, uint32_t* abort_flag,
+                                 int64_t* status) {
+  if (threadIdx.x != 0) return;
+  uint32_t it = 0;
+  while (__hip_atomic_load(word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < value)
+    if (!keep_waiting(it, abort_flag, status)) return;
+}
+
 static hipError_t link_wait(rq_handle h, int l, hipStream_t s) {
   if (!link_on_words(h, l)) return hipStreamWaitEvent(s, h->link_ev[l], 0);
-  return hipStreamWaitValue64(s, link_word(h, l), h->link_count[l], hipStreamWaitValueGte,
-                              ~0ull);
+  hipLaunchKernelGGL(wait_word_kernel, dim3(1), dim3(64), 0, s, link_word(h, l),
+                     h->link_count[l], h->sync + 1, h->status);
+  return hipGetLastError();
 }
 
 rq_status run_sample_qrcp(rq_handle h, double* B, int64_t ldb, int ell, int64_t N, int steps,
