@@ -189,8 +189,8 @@ static int64_t panel_prep_words(int64_t M, int bj);
 // streams do not run at the same time (a profiler's counter collection,
 // kernel serialization): there a waiting kernel would wait for a kernel that
 // cannot start.  h->link_values holds the choice for the current call.
-enum { kLinkZ = 0, kLinkU, kLinkQ, kLinkP };
-static bool link_on_words(rq_handle h, int l) { return h->link_values; }
+enum { kLinkZ = 0, kLinkU, kLinkQ, kLinkP, kCallStart };
+static bool link_on_words(rq_handle h, int /*link*/) { return h->link_values; }
 // Each of two one-wave kernels, one per stream, sets its own flag and waits
 // (at most `ticks` of the wall clock) for the other's: both see each other only
 // when the two streams' kernels run at the same time.  words: u32[4], zero
@@ -803,6 +803,13 @@ static rq_status rqrcp_core(rq_handle h, int64_t m, int64_t n, int64_t k, int64_
   // the panels, the widest persistent kernels of the loop, take panel_groups(m)
   // compute units at most; a pending wait on the words may hold one more
   h->link_values = h->words_ok && panel_groups(m) < h->cus;
+  // A word wait's spin is bounded, so the second stream must not start its
+  // first wait of this call before the caller's stream gets here: the caller's
+  // earlier work may take longer than that bound.  One event orders the two.
+  if (h->link_values) {
+    RQ_CHECK(h, hipEventRecord(h->link_ev[kCallStart], s));
+    RQ_CHECK(h, hipStreamWaitEvent(h->side, h->link_ev[kCallStart], 0));
+  }
   // The update of the rows below R12 runs on the side stream.  It is handed to
   // that stream only after the next block's sample QRCP is queued and waits on
   // a link signalled right before that launch: the persistent kernel needs

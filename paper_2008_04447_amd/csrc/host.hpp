@@ -71,7 +71,7 @@ struct rq_handle_s {
   // the RQRCP block loop's links between its two streams: device words with
   // the count each last had written, or events (see link_signal in api.hip)
   uint64_t link_count[4] = {0, 0, 0, 0};
-  hipEvent_t link_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t link_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // [4]: a call's start
   bool link_values = true;     // the current call orders the streams through the words
   bool words_ok = false;       // kernels of two streams were seen running at the same time
   double* scratch = nullptr;   // device address of the static scratch array (rq_sample_qrcp_noalloc)
