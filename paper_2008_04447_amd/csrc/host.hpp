@@ -173,8 +173,10 @@ rq_status gemm_lx_bf16_reduced(rq_handle h, int cls, GemmArgsF g, double* part, 
 // doubles of workspace that hold the BF16 staging of an operand with K columns
 inline size_t bf16_stage_doubles(int64_t K) { return (size_t)(bf16_stage_elems(K) + 3) / 4; }
 size_t sketch_part_doubles_bf16(int ell, int64_t m, int64_t n);
-// `queued`, when given, is recorded on the handle's stream right before the
-// kernel launch (work that waits on it becomes ready together with the launch).
+// `signal_side` releases the RQRCP block loop's trailing update on the side
+// stream (link Z): the kernel writes the link's word once all its workgroups
+// hold their compute units, or, where the call orders its streams with
+// events, the link's event is recorded right before the launch.
 // `panel_rec`, when given, is the record area of the panel that follows (M
 // rows, bj columns): it is prepared together with the sample's records, and
 // that panel is then run with `prepared` set.  `groups` is the workgroup
